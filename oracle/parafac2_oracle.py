@@ -1,0 +1,268 @@
+"""Plain FP64 CPU oracle for one PARAFAC2-ALS iteration on sparse irregular slices.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module: it exists so that tests/, the smoke check and the CPU
+baseline of the benchmark can check the HIP path against a slow, obviously
+correct implementation written from the paper (Perros et al., "SPARTan:
+Scalable PARAFAC2 for Large & Sparse Data", KDD'17).  It shares no code with
+the HIP path.
+
+Everything is float64 (the input values are float32 and are upcast exactly).
+The oracle follows the paper's algorithms in their order and notation:
+
+* the Q-step is the orthogonal Procrustes solution of Sec. "Classical
+  Algorithm for PARAFAC2", objective (procrustes_obj): SVD of H S_k V^T X_k^T,
+  Q_k = Z_k P_k^T (Algorithm "PARAFAC2-ALS", the first loop over k);
+* Y_k = Q_k^T X_k is formed explicitly (same algorithm, second loop over k);
+* the MTTKRPs are computed from their plain definitions, equations (mttkrp1),
+  (mttkrp2), (mttkrp3): M^(n) = Y_(n) (Khatri-Rao product), with the
+  matricizations of Sec. "Tensors and Tensor Operations" written out as
+  sparse matrices (only the nonzero columns of each Y_k are stored, as the
+  overview of Sec. "The SPARTan approach" notes they are the only nonzeros);
+* one CP-ALS iteration (Algorithm "CP-ALS") updates H, V, W with
+  pseudo-inverses of the Hadamard products of Grams.
+
+Readings of points the paper leaves open (each is listed in the design notes):
+
+* Q-step SVD (garbled in the text): the SVD of the R x I_k matrix
+  H S_k V^T X_k^T is written P diag(sigma) Z^T, and Q_k = Z P^T; the rank-R
+  truncation is the thin SVD (I_k >= R is required).
+* Normalisation (Algorithm "CP-ALS", "Normalize columns"): H and V get unit
+  2-norm columns after their updates and the norms are dropped; W is not
+  normalised (S_k = diag(W(k,:)) carries the scale, Sec. "CP Decomposition").
+  Dropping the norms does not change the iterate after the next least-squares
+  update, because each update absorbs a column scaling of the factors it holds
+  fixed.
+* Pseudo-inverse: eigen-decomposition of the symmetric R x R matrix,
+  eigenvalues <= R * eps64 * lambda_max are dropped.
+* Loss and fit: loss = sum_k ||X_k - Q_k H S_k V^T||_F^2 (the objective of
+  Sec. "Classical Algorithm for PARAFAC2"), fit = 1 - loss / sum_k ||X_k||_F^2,
+  evaluated after the W update of the iteration.
+* Projection of new subjects (serving) is not in the paper: with V and H
+  fixed, alternate the same Q-step and the least-squares update of one row of
+  W (the mode-3 MTTKRP row, equation (mttkrp3_row_wise), times the
+  pseudo-inverse of (V^T V) * (H^T H)), starting from w = 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+EPS64 = np.finfo(np.float64).eps
+
+
+# ---------------------------------------------------------------------------
+# input slices
+# ---------------------------------------------------------------------------
+
+def slices_to_list(subj_ptr, row_ptr, col, val, J):
+    """The collection {X_k} as scipy CSR matrices in float64."""
+    out = []
+    K = len(subj_ptr) - 1
+    for k in range(K):
+        r0, r1 = int(subj_ptr[k]), int(subj_ptr[k + 1])
+        z0, z1 = int(row_ptr[r0]), int(row_ptr[r1])
+        out.append(sp.csr_matrix(
+            (np.asarray(val[z0:z1], dtype=np.float64), np.asarray(col[z0:z1]),
+             np.asarray(row_ptr[r0:r1 + 1] - row_ptr[r0])), shape=(r1 - r0, J)))
+    return out
+
+
+def norm_x_sq(Xs):
+    """sum_k ||X_k||_F^2."""
+    return float(sum(float(X.data @ X.data) for X in Xs))
+
+
+# ---------------------------------------------------------------------------
+# building blocks
+# ---------------------------------------------------------------------------
+
+def khatri_rao(A, B):
+    """Column-wise Kronecker product A (.) B: row k*B.shape[0] + j is
+    A[k, :] * B[j, :] (Sec. "Tensors and Tensor Operations")."""
+    K, R = A.shape
+    J = B.shape[0]
+    return (A[:, None, :] * B[None, :, :]).reshape(K * J, R)
+
+
+def pinv_sym(N):
+    """Moore-Penrose pseudo-inverse of a symmetric PSD matrix via its
+    eigen-decomposition; eigenvalues <= R * eps * lambda_max are dropped."""
+    lam, E = np.linalg.eigh(N)
+    lmax = max(float(lam.max()), 0.0)
+    keep = lam > N.shape[0] * EPS64 * lmax
+    inv = np.zeros_like(lam)
+    inv[keep] = 1.0 / lam[keep]
+    return (E * inv) @ E.T
+
+
+def procrustes_q(X, H, w, V):
+    """Q-step for one subject (Sec. "Classical Algorithm for PARAFAC2",
+    objective (procrustes_obj)): SVD of H S_k V^T X_k^T = P diag(s) Z^T,
+    Q_k = Z P^T (I_k x R, orthonormal columns)."""
+    HSVt = (H * w) @ V.T  # R x J
+    M = np.asarray((X @ HSVt.T).T)  # H S_k V^T X_k^T, R x I_k
+    P, s, Zt = np.linalg.svd(M, full_matrices=False)
+    return Zt.T @ P.T
+
+
+def y_slice(Q, X):
+    """Y_k = Q_k^T X_k restricted to the nonzero columns of X_k (the other
+    columns of Y_k are exactly zero).  Returns (cols, Y_k[:, cols])."""
+    cols = np.unique(X.indices)
+    Xd = X[:, cols].toarray()
+    return cols, Q.T @ Xd
+
+
+# ---------------------------------------------------------------------------
+# matricizations of Y (R x J x K) and the plain MTTKRP definitions
+# ---------------------------------------------------------------------------
+
+def unfold_y(Ys, R, J, n):
+    """Mode-n matricization of the intermediate tensor Y (R x J x K) as a
+    sparse matrix, with Kolda's column ordering:
+      n=1: R x (J*K), column j + J*k;
+      n=2: J x (R*K), column r + R*k;
+      n=3: K x (R*J), column r + R*j."""
+    K = len(Ys)
+    rows, cols, vals = [], [], []
+    for k, (cj, Yk) in enumerate(Ys):
+        c = len(cj)
+        rr = np.repeat(np.arange(R), c)
+        jj = np.tile(cj, R)
+        v = Yk.reshape(-1)
+        if n == 1:
+            rows.append(rr); cols.append(jj + J * k)
+        elif n == 2:
+            rows.append(jj); cols.append(rr + R * k)
+        else:
+            rows.append(np.full(R * c, k)); cols.append(rr + R * jj)
+        vals.append(v)
+    shape = {1: (R, J * K), 2: (J, R * K), 3: (K, R * J)}[n]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=shape)
+
+
+def mttkrp(Ys, H, V, W, n):
+    """Plain definitions: M1 = Y_(1)(W (.) V) (mttkrp1), M2 = Y_(2)(W (.) H)
+    (mttkrp2), M3 = Y_(3)(V (.) H) (mttkrp3)."""
+    R, J, K = H.shape[0], V.shape[0], W.shape[0]
+    Yn = unfold_y(Ys, R, J, n)
+    if n == 1:
+        kr = khatri_rao(W, V)
+    elif n == 2:
+        kr = khatri_rao(W, H)
+    else:
+        kr = khatri_rao(V, H)
+    return np.asarray(Yn @ kr)
+
+
+def mttkrp_per_slice(Ys, H, V, W, n):
+    """The per-slice forms of Sec. "Methodology" (Algorithm "MTTKRP for
+    SPARTan"): (mttkrp1_3), (mttkrp2_3), (mttkrp3_row_wise).  Used only by
+    the oracle's own self-tests, as a second route to the same numbers."""
+    R, J, K = H.shape[0], V.shape[0], W.shape[0]
+    if n == 1:
+        M = np.zeros((R, R))
+        for k, (cj, Yk) in enumerate(Ys):
+            M += (Yk @ V[cj]) * W[k]
+        return M
+    if n == 2:
+        M = np.zeros((J, R))
+        for k, (cj, Yk) in enumerate(Ys):
+            M[cj] += (Yk.T @ H) * W[k]
+        return M
+    M = np.zeros((K, R))
+    for k, (cj, Yk) in enumerate(Ys):
+        M[k] = np.sum(H * (Yk @ V[cj]), axis=0)
+    return M
+
+
+# ---------------------------------------------------------------------------
+# one PARAFAC2-ALS iteration
+# ---------------------------------------------------------------------------
+
+def normalize_cols(A):
+    n = np.linalg.norm(A, axis=0)
+    n = np.where(n > 1e-300, n, 1.0)
+    return A / n
+
+
+def loss_dense(Xs, Qs, H, V, W):
+    """sum_k ||X_k - Q_k H S_k V^T||_F^2, computed densely."""
+    tot = 0.0
+    for k, X in enumerate(Xs):
+        D = X.toarray() - Qs[k] @ ((H * W[k]) @ V.T)
+        tot += float(np.sum(D * D))
+    return tot
+
+
+def loss_expanded(nx2, M3, W, V, H):
+    """The same loss when every Q_k has orthonormal columns:
+    ||X||^2 - 2 <W, M3> + sum_k w_k^T ((V^T V) * (H^T H)) w_k."""
+    N3 = (V.T @ V) * (H.T @ H)
+    return nx2 - 2.0 * float(np.sum(W * M3)) + float(np.sum((W @ N3) * W))
+
+
+def iterate(Xs, H, V, W, nx2=None, dense_loss=True, normalize=True):
+    """One PARAFAC2-ALS iteration (Algorithm "PARAFAC2-ALS" body: Q-step,
+    build {Y_k}, one CP-ALS iteration (Algorithm "CP-ALS"), S_k <- diag(W(k,:))).
+    Returns the new (H, V, W) and a dict with Q, Y, M1, M2, M3, loss, fit."""
+    R = H.shape[0]
+    if nx2 is None:
+        nx2 = norm_x_sq(Xs)
+    Qs = [procrustes_q(X, H, W[k], V) for k, X in enumerate(Xs)]
+    Ys = [y_slice(Qs[k], X) for k, X in enumerate(Xs)]
+    # mode 1: H <- Y_(1)(W (.) V)(W^T W * V^T V)^+, normalise
+    M1 = mttkrp(Ys, H, V, W, 1)
+    H1 = M1 @ pinv_sym((W.T @ W) * (V.T @ V))
+    if normalize:
+        H1 = normalize_cols(H1)
+    # mode 2: V <- Y_(2)(W (.) H)(W^T W * H^T H)^+, normalise
+    M2 = mttkrp(Ys, H1, V, W, 2)
+    V1 = M2 @ pinv_sym((W.T @ W) * (H1.T @ H1))
+    if normalize:
+        V1 = normalize_cols(V1)
+    # mode 3: W <- Y_(3)(V (.) H)(V^T V * H^T H)^+
+    M3 = mttkrp(Ys, H1, V1, W, 3)
+    W1 = M3 @ pinv_sym((V1.T @ V1) * (H1.T @ H1))
+    if dense_loss:
+        loss = loss_dense(Xs, Qs, H1, V1, W1)
+    else:
+        loss = loss_expanded(nx2, M3, W1, V1, H1)
+    return H1, V1, W1, dict(Q=Qs, Y=Ys, M1=M1, M2=M2, M3=M3, loss=loss, fit=1.0 - loss / nx2)
+
+
+
+def run(Xs, H, V, W, n_iter, dense_loss=True):
+    """n_iter iterations from (H, V, W); returns the final state and the list
+    of per-iteration info dicts."""
+    nx2 = norm_x_sq(Xs)
+    hist = []
+    for _ in range(n_iter):
+        H, V, W, info = iterate(Xs, H, V, W, nx2, dense_loss)
+        hist.append(info)
+    return H, V, W, hist
+
+
+# ---------------------------------------------------------------------------
+# projection of a new subject onto fixed (V, H)
+# ---------------------------------------------------------------------------
+
+def project(X, V, H, n_steps=10, w0=None):
+    """Alternate, n_steps times, the Q-step for this subject and the
+    least-squares update of its row of W with V and H fixed:
+    w <- diag(H^T Y V) ((V^T V) * (H^T H))^+   (equation (mttkrp3_row_wise)).
+    Returns (Q, w, loss) with Q from the last Q-step and w from the last
+    update."""
+    R = H.shape[0]
+    w = np.ones(R) if w0 is None else np.asarray(w0, dtype=np.float64).copy()
+    N3p = pinv_sym((V.T @ V) * (H.T @ H))
+    Q = None
+    for _ in range(n_steps):
+        Q = procrustes_q(X, H, w, V)
+        cj, Y = y_slice(Q, X)
+        m3 = np.sum(H * (Y @ V[cj]), axis=0)
+        w = m3 @ N3p
+    D = X.toarray() - Q @ ((H * w) @ V.T)
+    return Q, w, float(np.sum(D * D))

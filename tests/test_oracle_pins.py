@@ -1,0 +1,343 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test ties one part of the oracle to something other than itself: a dense
+brute-force construction of the tensor unfoldings, the textbook properties of
+the orthogonal Procrustes solution, least squares on the explicit Khatri-Rao
+product, the monotone ALS objective, a closed form at R = 1, exact recovery of
+planted noise-free models, and hand-derived values in tests/golden/.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from datagen import gen_config, gen_init, gen_planted, gen_slices, take_subjects
+from datagen.synth import _poisson_plus_one
+from oracle import parafac2_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _xs(X):
+    return O.slices_to_list(X.subj_ptr, X.row_ptr, X.col, X.val, X.J)
+
+
+def _small(K=12, J=9, R=3, ik=(3, 6), lam=2.0, seed=7):
+    X = gen_slices(K, J, ik, _poisson_plus_one(lam), "uniform", [seed])
+    return X, R
+
+
+def _dense_tensor(Ys, R, J):
+    K = len(Ys)
+    T = np.zeros((R, J, K))
+    for k, (cj, Yk) in enumerate(Ys):
+        T[:, cj, k] = Yk
+    return T
+
+
+def _unfold_dense(T, n):
+    # Kolda's mode-n unfolding: mode-n fibers become columns, remaining indices
+    # in increasing order with the first varying fastest (Fortran order).
+    return np.reshape(np.moveaxis(T, n - 1, 0), (T.shape[n - 1], -1), order="F")
+
+
+def _kr_dense(A, B):
+    # column r of A (.) B is kron(A[:, r], B[:, r])
+    return np.stack([np.kron(A[:, r], B[:, r]) for r in range(A.shape[1])], axis=1)
+
+
+def _state(X, R, seed=3):
+    rng = np.random.default_rng(seed)
+    H = rng.standard_normal((R, R))
+    V = rng.random((X.J, R))
+    W = 0.5 + rng.random((X.K, R))
+    return H, V, W
+
+
+# ---------------------------------------------------------------------------
+# P-1: the three MTTKRPs against a dense brute force
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_mttkrp_matches_dense_bruteforce(seed):
+    X, R = _small(seed=seed)
+    Xs = _xs(X)
+    H, V, W = _state(X, R, seed)
+    Qs = [O.procrustes_q(Xk, H, W[k], V) for k, Xk in enumerate(Xs)]
+    Ys = [O.y_slice(Qs[k], Xk) for k, Xk in enumerate(Xs)]
+    T = _dense_tensor(Ys, R, X.J)
+    # the dense tensor's slices are Q_k^T X_k on all columns
+    for k, Xk in enumerate(Xs):
+        np.testing.assert_allclose(T[:, :, k], Qs[k].T @ Xk.toarray(), atol=1e-13)
+    bf = {1: _unfold_dense(T, 1) @ _kr_dense(W, V),
+          2: _unfold_dense(T, 2) @ _kr_dense(W, H),
+          3: _unfold_dense(T, 3) @ _kr_dense(V, H)}
+    for n in (1, 2, 3):
+        M = O.mttkrp(Ys, H, V, W, n)
+        Mps = O.mttkrp_per_slice(Ys, H, V, W, n)
+        scale = np.linalg.norm(bf[n])
+        assert np.linalg.norm(M - bf[n]) <= 1e-12 * scale
+        assert np.linalg.norm(Mps - bf[n]) <= 1e-12 * scale
+
+
+def test_mode3_is_columnwise_inner_product():
+    # equation (mttkrp3_colwise): M3(k, r) = H(:, r)^T Y_k V(:, r)
+    X, R = _small(seed=5)
+    Xs = _xs(X)
+    H, V, W = _state(X, R, 5)
+    Ys = [O.y_slice(O.procrustes_q(Xk, H, W[k], V), Xk) for k, Xk in enumerate(Xs)]
+    M3 = O.mttkrp(Ys, H, V, W, 3)
+    T = _dense_tensor(Ys, R, X.J)
+    for k in range(X.K):
+        for r in range(R):
+            assert abs(M3[k, r] - H[:, r] @ T[:, :, k] @ V[:, r]) <= 1e-12 * (1 + abs(M3[k, r]))
+
+
+# ---------------------------------------------------------------------------
+# P-2: orthogonal Procrustes
+# ---------------------------------------------------------------------------
+
+def _rand_orth(rng, n, r):
+    q, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    return q
+
+
+def test_procrustes_textbook_properties():
+    rng = np.random.default_rng(11)
+    I, J, R = 9, 7, 4
+    Xd = rng.random((I, J))
+    X = sp.csr_matrix(Xd)
+    H = rng.standard_normal((R, R))
+    w = 0.5 + rng.random(R)
+    V = rng.random((J, R))
+    Q = O.procrustes_q(X, H, w, V)
+    B = Xd @ V @ np.diag(w) @ H.T  # the matrix whose polar factor Q is
+    np.testing.assert_allclose(Q.T @ Q, np.eye(R), atol=1e-13)
+    s = np.linalg.svd(B, compute_uv=False)
+    assert abs(np.trace(Q.T @ B) - s.sum()) <= 1e-12 * s.sum()
+    for _ in range(100):
+        Qp = _rand_orth(rng, I, R)
+        assert np.trace(Qp.T @ B) <= np.trace(Q.T @ B) + 1e-12
+    # full rank: Q = B (B^T B)^{-1/2}
+    lam, E = np.linalg.eigh(B.T @ B)
+    np.testing.assert_allclose(Q, B @ (E / np.sqrt(lam)) @ E.T, atol=1e-11)
+    # the Procrustes objective itself: Q minimises ||X - Q H S V^T||
+    obj = np.linalg.norm(Xd - Q @ H @ np.diag(w) @ V.T)
+    for _ in range(50):
+        Qp = _rand_orth(rng, I, R)
+        assert obj <= np.linalg.norm(Xd - Qp @ H @ np.diag(w) @ V.T) + 1e-12
+
+
+def test_procrustes_special_cases():
+    rng = np.random.default_rng(12)
+    # R = 1: Q = b / ||b||
+    Xd = rng.random((6, 5))
+    V = rng.random((5, 1))
+    Q = O.procrustes_q(sp.csr_matrix(Xd), np.array([[2.0]]), np.array([0.7]), V)
+    b = Xd @ V
+    np.testing.assert_allclose(Q, b / np.linalg.norm(b), atol=1e-14)
+    # B already orthonormal: Q = B
+    Qo = _rand_orth(rng, 8, 3)
+    # X V = Qo with X = Qo V^+ for V with orthonormal columns, H = I, w = 1
+    Vo = _rand_orth(rng, 6, 3)
+    Xd = Qo @ Vo.T
+    Q = O.procrustes_q(sp.csr_matrix(Xd), np.eye(3), np.ones(3), Vo)
+    np.testing.assert_allclose(Q, Qo, atol=1e-13)
+
+
+def test_procrustes_ambiguous_case_keeps_objective():
+    # w with a zero entry makes B rank deficient: several Q are optimal, check
+    # only the invariant tr(Q^T B) = ||B||_* and orthonormality
+    rng = np.random.default_rng(13)
+    Xd = rng.random((7, 6))
+    H = rng.standard_normal((3, 3))
+    V = rng.random((6, 3))
+    w = np.array([1.0, 0.0, 0.5])
+    Q = O.procrustes_q(sp.csr_matrix(Xd), H, w, V)
+    B = Xd @ V @ np.diag(w) @ H.T
+    np.testing.assert_allclose(Q.T @ Q, np.eye(3), atol=1e-13)
+    assert abs(np.trace(Q.T @ B) - np.linalg.svd(B, compute_uv=False).sum()) <= 1e-12 * np.abs(B).sum()
+
+
+# ---------------------------------------------------------------------------
+# P-3: least-squares updates against lstsq on the explicit Khatri-Rao product
+# ---------------------------------------------------------------------------
+
+def test_updates_are_least_squares_on_explicit_kr():
+    X, R = _small(K=10, J=8, R=3, seed=21)
+    Xs = _xs(X)
+    H, V, W = _state(X, R, 21)
+    H1, V1, W1, info = O.iterate(Xs, H, V, W, normalize=False)
+    T = _dense_tensor(info["Y"], R, X.J)
+    # H solves min ||Y_(1) - H (W (.) V)^T||
+    Hl = np.linalg.lstsq(_kr_dense(W, V), _unfold_dense(T, 1).T, rcond=None)[0].T
+    np.testing.assert_allclose(H1, Hl, rtol=1e-9, atol=1e-10)
+    # V solves min ||Y_(2) - V (W (.) H1)^T||
+    Vl = np.linalg.lstsq(_kr_dense(W, H1), _unfold_dense(T, 2).T, rcond=None)[0].T
+    np.testing.assert_allclose(V1, Vl, rtol=1e-9, atol=1e-10)
+    # W solves min ||Y_(3) - W (V1 (.) H1)^T||
+    Wl = np.linalg.lstsq(_kr_dense(V1, H1), _unfold_dense(T, 3).T, rcond=None)[0].T
+    np.testing.assert_allclose(W1, Wl, rtol=1e-9, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# P-4, P-5, P-6: objective, fit formula, normalisation
+# ---------------------------------------------------------------------------
+
+def test_loss_monotone_config1():
+    X, R = gen_config(1)
+    Xs = _xs(X)
+    H, V, W = gen_init(X.J, X.K, R, [170304219, 1, 1])
+    H, V, W, hist = O.run(Xs, H, V, W, 20)
+    losses = [h["loss"] for h in hist]
+    for a, b in zip(losses, losses[1:]):
+        assert b <= a * (1 + 1e-12)
+    assert 0.0 < hist[-1]["fit"] < 1.0
+
+
+def test_dense_loss_equals_expanded_formula():
+    X, R = gen_config(1)
+    Xs = _xs(X)
+    H, V, W = gen_init(X.J, X.K, R, [170304219, 1, 1])
+    nx2 = O.norm_x_sq(Xs)
+    for _ in range(3):
+        H, V, W, info = O.iterate(Xs, H, V, W, nx2, dense_loss=True)
+        le = O.loss_expanded(nx2, info["M3"], W, V, H)
+        assert abs(le - info["loss"]) <= 1e-10 * nx2
+
+
+def test_normalisation_does_not_change_the_model():
+    X, R = _small(K=15, J=10, R=3, seed=31)
+    Xs = _xs(X)
+    H, V, W = _state(X, R, 31)
+    Ha, Va, Wa, ia = O.iterate(Xs, H, V, W, normalize=True)
+    Hb, Vb, Wb, ib = O.iterate(Xs, H, V, W, normalize=False)
+    for k in range(X.K):
+        Ua = ia["Q"][k] @ Ha @ np.diag(Wa[k]) @ Va.T
+        Ub = ib["Q"][k] @ Hb @ np.diag(Wb[k]) @ Vb.T
+        np.testing.assert_allclose(Ua, Ub, rtol=1e-10, atol=1e-12)
+    assert abs(ia["loss"] - ib["loss"]) <= 1e-10 * ia["loss"]
+
+
+# ---------------------------------------------------------------------------
+# P-7: recovery of planted noise-free models (PARAFAC2 unique for K >= 4)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("col_blocks", [False, True])
+def test_planted_model_recovered_from_near_truth(col_blocks):
+    X, truth = gen_planted(K=8, J=30, R=3, ik_range=(5, 12), seed=[41], col_blocks=col_blocks)
+    Xs = _xs(X)
+    rng = np.random.default_rng(0)
+    H = truth["H"] + 1e-2 * rng.standard_normal(truth["H"].shape)
+    V = truth["V"] + 1e-2 * rng.standard_normal(truth["V"].shape)
+    W = truth["W"] + 1e-2 * rng.standard_normal(truth["W"].shape)
+    H, V, W, hist = O.run(Xs, H, V, W, 300, dense_loss=False)
+    # ALS converges linearly here; the float32 rounding of the inputs alone
+    # would only cap the fit near 1 - 1e-15
+    assert hist[-1]["fit"] >= 1 - 1e-8
+    fits = [h["fit"] for h in hist]
+    assert all(b >= a - 1e-13 for a, b in zip(fits, fits[1:]))
+    # the recovered V spans the true columns (up to scale and sign)
+    Vt = truth["V"] / np.linalg.norm(truth["V"], axis=0)
+    cong = np.abs(Vt.T @ V)
+    assert np.all(cong.max(axis=1) > 0.999)
+
+
+def test_planted_model_recovered_from_default_init():
+    # From the default start (H = I, W = 1, V random) PARAFAC2-ALS passes through
+    # a long swamp before it reaches the planted model; this recorded seed
+    # reaches it within 2000 iterations.
+    X, truth = gen_planted(K=50, J=30, R=3, ik_range=(6, 12), seed=[45], col_blocks=True)
+    Xs = _xs(X)
+    H, V, W = gen_init(X.J, X.K, 3, [45, 1])
+    H, V, W, hist = O.run(Xs, H, V, W, 2000, dense_loss=False)
+    assert hist[-1]["fit"] >= 1 - 1e-10
+    Vt = truth["V"] / np.linalg.norm(truth["V"], axis=0)
+    cong = np.abs(Vt.T @ V)
+    assert np.all(cong.max(axis=1) > 0.9999)
+
+
+# ---------------------------------------------------------------------------
+# P-8: R = 1 closed form
+# ---------------------------------------------------------------------------
+
+def test_rank_one_closed_form():
+    # With R = 1, min sum_k ||X_k - c_k q_k v^T|| over unit q_k, v gives the top
+    # eigenvector v of sum_k X_k^T X_k and fit* = lambda_max / ||X||^2.
+    X = gen_slices(60, 40, (3, 8), _poisson_plus_one(3.0), "uniform", [51])
+    Xs = _xs(X)
+    G = sum((Xk.T @ Xk).toarray() for Xk in Xs)
+    lam, E = np.linalg.eigh(G)
+    nx2 = O.norm_x_sq(Xs)
+    fit_star = lam[-1] / nx2
+    H, V, W = gen_init(X.J, X.K, 1, [51, 1])
+    H, V, W, hist = O.run(Xs, H, V, W, 300, dense_loss=False)
+    assert abs(hist[-1]["fit"] - fit_star) <= 1e-7
+    assert abs(abs(float(E[:, -1] @ V[:, 0])) - 1.0) <= 1e-6
+
+
+def test_golden_hand_derived_cases():
+    with open(os.path.join(GOLDEN, "rank_one_hand.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        K = len(c["slices"])
+        J = len(c["slices"][0][0])
+        Xs = [sp.csr_matrix(np.array(s, dtype=np.float64)) for s in c["slices"]]
+        H, V, W = np.eye(1), np.array(c["v0"], dtype=np.float64).reshape(J, 1), np.ones((K, 1))
+        H, V, W, hist = O.run(Xs, H, V, W, c["iters"], dense_loss=True)
+        assert abs(hist[-1]["fit"] - c["fit"]) <= c["tol"], c["name"]
+
+
+# ---------------------------------------------------------------------------
+# P-9, P-10: structure
+# ---------------------------------------------------------------------------
+
+def test_mode2_rows_outside_nonzero_columns_are_zero():
+    X, R = _small(K=5, J=60, R=3, lam=0.5, seed=61)
+    Xs = _xs(X)
+    H, V, W = _state(X, R, 61)
+    _, _, _, info = O.iterate(Xs, H, V, W)
+    used = np.zeros(X.J, bool)
+    used[np.unique(X.col)] = True
+    assert not used.all()
+    assert np.all(info["M2"][~used] == 0.0)
+
+
+def test_subject_permutation_invariance():
+    X, R = _small(K=10, J=9, R=3, seed=71)
+    Xs = _xs(X)
+    H, V, W = _state(X, R, 71)
+    perm = np.random.default_rng(1).permutation(X.K)
+    a = O.iterate(Xs, H, V, W)
+    b = O.iterate([Xs[p] for p in perm], H, V, W[perm])
+    np.testing.assert_allclose(b[0], a[0], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(b[1], a[1], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(b[2], a[2][perm], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(b[3]["M3"], a[3]["M3"][perm], rtol=1e-11, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P-12: projection of new subjects onto fixed (V, H)
+# ---------------------------------------------------------------------------
+
+def test_projection_recovers_planted_weights():
+    X, truth = gen_planted(K=6, J=25, R=3, ik_range=(6, 10), seed=[81])
+    Xs = _xs(X)
+    for k in range(X.K):
+        Q, w, loss = O.project(Xs[k], truth["V"], truth["H"], n_steps=200)
+        nk = float(Xs[k].data @ Xs[k].data)
+        assert loss <= 1e-12 * nk
+        np.testing.assert_allclose(w, truth["W"][k], rtol=1e-5)
+
+
+def test_projection_loss_monotone_over_steps():
+    X, R = _small(K=4, J=12, R=3, seed=91)
+    Xs = _xs(X)
+    rng = np.random.default_rng(91)
+    V, H = rng.random((X.J, R)), rng.standard_normal((R, R))
+    for k in range(X.K):
+        losses = [O.project(Xs[k], V, H, n_steps=s)[2] for s in range(1, 8)]
+        for a, b in zip(losses, losses[1:]):
+            assert b <= a * (1 + 1e-12) + 1e-14
