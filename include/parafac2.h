@@ -1,0 +1,201 @@
+/*
+ * parafac2.h -- C ABI of the MI355X (gfx950) PARAFAC2-ALS hot path.
+ *
+ * The method is SPARTan (Perros et al., "SPARTan: Scalable PARAFAC2 for Large
+ * & Sparse Data", KDD'17).  Given K sparse slices X_k (I_k x J) and a target
+ * rank R, PARAFAC2 fits X_k ~ Q_k H S_k V^T with Q_k^T Q_k = I, S_k diagonal
+ * (Sec. "Model", equation (paratwo_basic)).  One ALS iteration (Algorithm
+ * "PARAFAC2-ALS") is:
+ *   1. the orthogonal Procrustes step, Q_k = polar(X_k V S_k H^T) for every
+ *      subject (objective (procrustes_obj));
+ *   2. one CP-ALS iteration (Algorithm "CP-ALS") on the tensor Y with frontal
+ *      slices Y_k = Q_k^T X_k, whose three MTTKRPs are computed slice by slice
+ *      over the nonzero columns of X_k only (Sec. "Methodology", Algorithm
+ *      "MTTKRP for SPARTan", equations (mttkrp1_3), (mttkrp2_3),
+ *      (mttkrp3_row_wise));
+ *   3. S_k <- diag(W(k,:)).
+ * The library never forms Y or Q_k during an iteration: every MTTKRP is
+ * rewritten in terms of per-subject R x R matrices and per-row R-vectors.
+ *
+ * Conventions for every call:
+ *   - return value: 0 (P2_OK) or a negative status; nothing aborts and nothing
+ *     throws across the ABI; parafac2_last_error() gives the text of the last
+ *     failure on the calling thread;
+ *   - matrices are row-major and 0-based;
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary CPU memory;
+ *   - stream is a hipStream_t passed as void* (NULL = default stream); all
+ *     device work of a context or model is enqueued on its stream;
+ *   - the caller owns every buffer it passes, including the workspace; the
+ *     library allocates no device memory.
+ */
+#ifndef PARAFAC2_H
+#define PARAFAC2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  P2_OK = 0,
+  P2_EINVAL = -1,  /* bad argument or input data (message says which)          */
+  P2_ENOMEM = -2,  /* workspace smaller than parafac2_workspace_size() asked for */
+  P2_EDEVICE = -3, /* a HIP call failed; the context is then unusable           */
+  P2_ESTATE = -4,  /* context or model is in a failed state                    */
+  P2_ENOTSUP = -5  /* valid input outside what this build supports (e.g. R)    */
+};
+
+#define PARAFAC2_ABI_VERSION 1
+
+/* Opaque handles.  A context holds one decomposition, a model holds fixed
+ * (V, H) for projecting new subjects.  Neither is thread-safe; calls that
+ * overlap on one handle race. */
+typedef struct parafac2_ctx parafac2_ctx;
+typedef struct parafac2_model parafac2_model;
+
+/* The input collection {X_k} (Algorithm "PARAFAC2-ALS", REQUIRE) as one
+ * concatenated CSR.  Subject k owns rows [subj_ptr[k], subj_ptr[k+1]); row i
+ * owns nonzeros [row_ptr[i], row_ptr[i+1]).  Columns are in [0, J) and
+ * strictly increasing within a row; values are finite.  Empty rows are
+ * accepted (they contribute nothing; the paper filters them, Sec.
+ * "Challenges of PARAFAC2 on sparse data").  Limits of this build:
+ * I_k >= R (the rank-R Procrustes factor needs I_k >= R), I_k <= 65535,
+ * nnz of one subject <= 65535, J <= 65536. */
+typedef struct {
+  int64_t K, J, n_rows, nnz;
+  const int64_t* subj_ptr; /* [K+1]      */
+  const int64_t* row_ptr;  /* [n_rows+1] */
+  const int32_t* col;      /* [nnz]      */
+  const float* val;        /* [nnz]      */
+} parafac2_csr;
+
+/* Options; a zero-initialised struct selects the defaults. */
+typedef struct {
+  double tau_polar;  /* eigenvalues of G_k = B_k^T B_k (B_k = X_k V S_k H^T)
+                        below tau_polar * lambda_max are dropped from the
+                        inverse square root in the Procrustes step;
+                        0 -> 1e-10                                           */
+  double tau_pinv;   /* eigenvalue cut of the R x R pseudo-inverses of the
+                        normal equations (Algorithm "CP-ALS"), relative to
+                        lambda_max; 0 -> R * 2.22e-16                         */
+  int32_t hot_cols;  /* columns whose mode-2 partial sums are kept in LDS;
+                        0 -> as many as fit, -1 -> none                       */
+  int32_t max_sweeps;/* cap on Jacobi sweeps per R x R eigenproblem; 0 -> 30 */
+  int32_t reserved[8];
+} parafac2_opts;
+
+/* ABI version of the loaded library (PARAFAC2_ABI_VERSION). */
+int parafac2_abi_version(void);
+
+/* Text of the last failing call on this thread ("" if none). */
+const char* parafac2_last_error(void);
+
+/* Host-only validation of a CSR whose pointers are HOST memory: shapes,
+ * monotone offsets, column range and order, finiteness, I_k >= R and the
+ * build limits above.  Writes a message to msg (if non-NULL).  Returns P2_OK,
+ * P2_EINVAL or P2_ENOTSUP.  Touches no GPU. */
+int parafac2_validate_host(const parafac2_csr* host_X, int32_t R, char* msg, size_t msg_len);
+
+/* Bytes of device workspace that parafac2_init needs for X (only the sizes
+ * K, J, n_rows, nnz of X are read) and rank R.  Touches no GPU. */
+int parafac2_workspace_size(const parafac2_csr* X, int32_t R, const parafac2_opts* opts,
+                            size_t* bytes);
+
+/* Create a context for one decomposition (Algorithm "PARAFAC2-ALS").
+ *   X          device CSR; read only during this call (it is validated on the
+ *              device and re-encoded into the workspace).
+ *   R          target rank.
+ *   H, V, W    device, row-major: H is R x R float64, V is J x R float32, W is
+ *              K x R float32 (S_k = diag(W(k,:))).  On entry the initial state
+ *              (Algorithm "PARAFAC2-ALS", "Initialize"); the context borrows
+ *              them until parafac2_destroy and updates them in place.
+ *   workspace  device buffer of at least parafac2_workspace_size() bytes,
+ *              256-byte aligned, borrowed until parafac2_destroy.
+ * Synchronises the stream once (validation result and column statistics).
+ * Errors: P2_EINVAL (shapes, data, small workspace), P2_ENOTSUP (R or sizes
+ * outside this build), P2_EDEVICE. */
+int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* H, float* V,
+                  float* W, void* workspace, size_t ws_bytes, void* stream,
+                  const parafac2_opts* opts);
+
+/* Run n_iters PARAFAC2-ALS iterations.  Each iteration is the Procrustes
+ * step, the mode-1 MTTKRP and H update, the mode-2 MTTKRP and V update, the
+ * mode-3 MTTKRP and W update (Algorithm "CP-ALS" order; H and V columns
+ * normalised, W keeps the scale).  On return H, V and W hold the new state.
+ * fit_host (host, n_iters entries, or NULL) receives per iteration
+ * fit = 1 - loss / sum_k ||X_k||_F^2 with
+ * loss = sum_k ||X_k - Q_k H S_k V^T||_F^2 evaluated after the W update.
+ * Enqueues on the context's stream; synchronises only if fit_host != NULL. */
+int parafac2_iterate(parafac2_ctx* c, int32_t n_iters, double* fit_host);
+
+/* The three MTTKRPs of the last iteration (equations (mttkrp1), (mttkrp2),
+ * (mttkrp3)), for parity checks.  Device pointers, any may be NULL:
+ * M1 R x R float64, M2 J x R float32, M3 K x R float32.  Enqueued on the
+ * context's stream. */
+int parafac2_get_mttkrp(parafac2_ctx* c, double* M1, float* M2, float* M3);
+
+/* Q_k of the last Procrustes step for subjects [k0, k1) (Algorithm
+ * "PARAFAC2-ALS": U_k = Q_k H after the loop).  Q (device, float32) receives
+ * the rows of those subjects, (subj_ptr[k1] - subj_ptr[k0]) x R, row-major.
+ * P2_ESTATE if no iteration has run since init. */
+int parafac2_get_q(parafac2_ctx* c, int64_t k0, int64_t k1, float* Q);
+
+/* Per-phase device timing (for benchmarks).  While profiling is on, every
+ * kernel launch of parafac2_iterate is bracketed by HIP events recorded on the
+ * context's stream; parafac2_get_profile synchronises the stream and returns,
+ * per phase, the summed elapsed milliseconds and the number of launches since
+ * profiling was switched on.  Phases (P2_PHASE_*): Procrustes step of the
+ * first iteration, H solve (W^T W and the R x R solve), mode-2 MTTKRP, V
+ * update (V = M2 N2^+, normalisation, N3), mode-3 MTTKRP with the W update and
+ * the next Procrustes step, fit. */
+enum {
+  P2_PHASE_ALPHA = 0,
+  P2_PHASE_SOLVE_H = 1,
+  P2_PHASE_MODE2 = 2,
+  P2_PHASE_VUPDATE = 3,
+  P2_PHASE_GAMMA = 4,
+  P2_PHASE_FIT = 5,
+  P2_NPHASES = 6
+};
+int parafac2_set_profiling(parafac2_ctx* c, int32_t on);
+int parafac2_get_profile(parafac2_ctx* c, double* ms, int64_t* launches);
+
+/* Release a context (the caller's buffers are not freed). */
+void parafac2_destroy(parafac2_ctx* c);
+
+/* ---- projection of new subjects onto fixed (V, H) --------------------------
+ * Not in the paper: it applies the subject-wise half of Algorithm
+ * "PARAFAC2-ALS" with V and H fixed.  For each request subject, starting from
+ * w (R), repeat n_steps times: Q = polar(X V diag(w) H^T) (objective
+ * (procrustes_obj)); w <- diag(H^T Q^T X V) ((V^T V) * (H^T H))^+
+ * (equation (mttkrp3_row_wise) and the W update of Algorithm "CP-ALS").  */
+
+/* Bytes of device workspace for a model of J x R. */
+int parafac2_model_workspace_size(int64_t J, int32_t R, size_t* bytes);
+
+/* Create a model.  V (device, J x R float32) and H (device, R x R float64)
+ * are copied into the workspace (device, >= parafac2_model_workspace_size
+ * bytes, borrowed until parafac2_model_destroy).  Synchronises once. */
+int parafac2_model_create(parafac2_model** out, int64_t J, int32_t R, const float* V,
+                          const double* H, void* workspace, size_t ws_bytes, void* stream);
+
+/* Project req->K subjects (device CSR with req->J equal to the model's J,
+ * I_k >= R).  Subject k's result depends only on its own slice.
+ *   w0      device K x R float32 start values, or NULL for all ones;
+ *   Q_out   device (sum_k I_k) x R float32 (rows in req's row order), or NULL;
+ *   w_out   device K x R float32 (required);
+ *   loss_out device K float64 ||X_k - Q_k H diag(w_k) V^T||_F^2, or NULL.
+ * stream: NULL uses the model's stream.  Nothing is synchronised. */
+int parafac2_project(parafac2_model* m, const parafac2_csr* req, int32_t n_steps, const float* w0,
+                     float* Q_out, float* w_out, double* loss_out, void* stream);
+
+void parafac2_model_destroy(parafac2_model* m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARAFAC2_H */

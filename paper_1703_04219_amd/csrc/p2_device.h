@@ -1,0 +1,368 @@
+// Device building blocks of the PARAFAC2-ALS hot path on gfx950 (CDNA4).
+//
+// Work layout used by every per-subject kernel: a subject is owned by a
+// "group" of NC consecutive lanes of one 64-wide wavefront (NC = R rounded up
+// to even).  Lane c of the group owns column c of every R x R matrix of that
+// subject, so R x R products are R-wide FMA loops per lane, and the Jacobi
+// eigen-solver exchanges whole columns between lane pairs with shuffles.
+// Several groups share a wavefront (6 at R = 10, 1 at R = 40); all data
+// exchange inside a group goes through shuffles or the group's own LDS
+// region, so no workgroup barrier is needed inside the subject loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace p2 {
+
+constexpr int kWave = 64;
+
+template <int R>
+struct Geo {
+  static constexpr int NC = (R & 1) ? R + 1 : R;  // lanes per subject group
+  static constexpr int GPW = kWave / NC;           // groups per wavefront
+  static constexpr int LDV = (R + 3) & ~3;         // padded row stride of V/M2
+  // rows of one gather chunk: whole multiples of the group width, about 24
+  static constexpr int CH = NC * ((24 + NC - 1) / NC);
+};
+
+// Orders LDS traffic between lanes of one wavefront (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// Slice access.  XEnc is the re-encoded collection built at init (16-bit
+// columns relabelled by frequency, 16-bit row starts relative to the subject),
+// XRaw is the caller's plain CSR (used for projection requests).
+// ---------------------------------------------------------------------------
+
+struct Subj {
+  int64_t z0;  // first nonzero
+  int64_t r0;  // first row
+  int nrows;
+  int nnz;
+};
+
+struct XEnc {
+  const int64_t* zbase;
+  const int64_t* rbase;
+  const uint16_t* rstart;
+  const uint16_t* col;
+  const float* val;
+  __device__ __forceinline__ Subj subj(int64_t k) const {
+    Subj s;
+    s.z0 = zbase[k];
+    s.r0 = rbase[k];
+    s.nrows = (int)(rbase[k + 1] - s.r0);
+    s.nnz = (int)(zbase[k + 1] - s.z0);
+    return s;
+  }
+  __device__ __forceinline__ void row(const Subj& s, int i, int& zs, int& ze) const {
+    zs = rstart[s.r0 + i];
+    ze = (i + 1 < s.nrows) ? (int)rstart[s.r0 + i + 1] : s.nnz;
+  }
+  __device__ __forceinline__ int colat(const Subj& s, int z) const { return col[s.z0 + z]; }
+  __device__ __forceinline__ float valat(const Subj& s, int z) const { return val[s.z0 + z]; }
+};
+
+struct XRaw {
+  const int64_t* subj_ptr;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const float* val;
+  __device__ __forceinline__ Subj subj(int64_t k) const {
+    Subj s;
+    s.r0 = subj_ptr[k];
+    s.nrows = (int)(subj_ptr[k + 1] - s.r0);
+    s.z0 = row_ptr[s.r0];
+    s.nnz = (int)(row_ptr[s.r0 + s.nrows] - s.z0);
+    return s;
+  }
+  __device__ __forceinline__ void row(const Subj& s, int i, int& zs, int& ze) const {
+    zs = (int)(row_ptr[s.r0 + i] - s.z0);
+    ze = (int)(row_ptr[s.r0 + i + 1] - s.z0);
+  }
+  __device__ __forceinline__ int colat(const Subj& s, int z) const { return col[s.z0 + z]; }
+  __device__ __forceinline__ float valat(const Subj& s, int z) const { return val[s.z0 + z]; }
+};
+
+// ---------------------------------------------------------------------------
+// Sparse gather (equation (mttkrp1_3): only the rows of V of the nonzero
+// columns of X_k are touched):  A(i,:) = sum_z x_z V(col_z, :) in FP32 for the
+// chunk rows [i0, i0 + n) of subject s, written to LDS as T (float or double).
+// V rows have stride LDV (16-byte aligned, zero padded).
+// ---------------------------------------------------------------------------
+template <int R, class XS, class T>
+__device__ __forceinline__ void gather_rows(const XS& X, const Subj& s, int i0, int n,
+                                            const float* __restrict__ V, T* A, int j) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int LDV = Geo<R>::LDV;
+#pragma nounroll
+  for (int ii = j; ii < n; ii += NC) {
+    float acc[LDV];
+#pragma unroll
+    for (int c = 0; c < LDV; ++c) acc[c] = 0.f;
+    int zs, ze;
+    X.row(s, i0 + ii, zs, ze);
+    for (int z = zs; z < ze; ++z) {
+      const int col = X.colat(s, z);
+      const float x = X.valat(s, z);
+      const float4* vr = reinterpret_cast<const float4*>(V + (size_t)col * LDV);
+#pragma unroll
+      for (int q = 0; q < LDV / 4; ++q) {
+        const float4 t = vr[q];
+        acc[4 * q + 0] = fmaf(x, t.x, acc[4 * q + 0]);
+        acc[4 * q + 1] = fmaf(x, t.y, acc[4 * q + 1]);
+        acc[4 * q + 2] = fmaf(x, t.z, acc[4 * q + 2]);
+        acc[4 * q + 3] = fmaf(x, t.w, acc[4 * q + 3]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) A[ii * R + c] = (T)acc[c];
+  }
+}
+
+// Two gathers of the same rows against two factor matrices (V_t and V_{t+1}).
+template <int R, class XS>
+__device__ __forceinline__ void gather_rows2(const XS& X, const Subj& s, int i0, int n,
+                                             const float* __restrict__ V0,
+                                             const float* __restrict__ V1, double* A0, double* A1,
+                                             int j) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int LDV = Geo<R>::LDV;
+#pragma nounroll
+  for (int ii = j; ii < n; ii += NC) {
+    float a0[LDV], a1[LDV];
+#pragma unroll
+    for (int c = 0; c < LDV; ++c) a0[c] = a1[c] = 0.f;
+    int zs, ze;
+    X.row(s, i0 + ii, zs, ze);
+    for (int z = zs; z < ze; ++z) {
+      const int col = X.colat(s, z);
+      const float x = X.valat(s, z);
+      const float4* v0 = reinterpret_cast<const float4*>(V0 + (size_t)col * LDV);
+      const float4* v1 = reinterpret_cast<const float4*>(V1 + (size_t)col * LDV);
+#pragma unroll
+      for (int q = 0; q < LDV / 4; ++q) {
+        const float4 t = v0[q];
+        const float4 u = v1[q];
+        a0[4 * q + 0] = fmaf(x, t.x, a0[4 * q + 0]);
+        a0[4 * q + 1] = fmaf(x, t.y, a0[4 * q + 1]);
+        a0[4 * q + 2] = fmaf(x, t.z, a0[4 * q + 2]);
+        a0[4 * q + 3] = fmaf(x, t.w, a0[4 * q + 3]);
+        a1[4 * q + 0] = fmaf(x, u.x, a1[4 * q + 0]);
+        a1[4 * q + 1] = fmaf(x, u.y, a1[4 * q + 1]);
+        a1[4 * q + 2] = fmaf(x, u.z, a1[4 * q + 2]);
+        a1[4 * q + 3] = fmaf(x, u.w, a1[4 * q + 3]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      A0[ii * R + c] = (double)a0[c];
+      A1[ii * R + c] = (double)a1[c];
+    }
+  }
+}
+
+// Gram rows from an LDS chunk: lane c (< R) accumulates row c of A^T B in
+// FP64 (products of the FP32 values are exact in FP64).
+template <int R>
+__device__ __forceinline__ void gram_accum(const double* A, const double* B, int n, int c,
+                                           double (&row)[R]) {
+  const int cc = c < R ? c : 0;
+#pragma nounroll
+  for (int ii = 0; ii < n; ++ii) {
+    const double a = A[ii * R + cc];
+#pragma unroll
+    for (int l = 0; l < R; ++l) row[l] = fma(a, B[ii * R + l], row[l]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi on the symmetric PSD matrix G, column per lane.
+// On entry lane j of the group holds g = G(:, j) and v = e_j (zero columns on
+// the padding lane).  Pairs of positions rotate and then swap ("caterpillar"
+// odd-even ordering: positions (2t, 2t+1) on even steps, (2t+1, 2t+2) on odd
+// steps; NC steps make every pair meet once).  At convergence G v_j = g_j with
+// orthonormal v_j, i.e. the v_j are eigenvectors of G and v_j^T g_j are the
+// eigenvalues.  A group stops rotating (and swapping) after a full sweep
+// without rotations, so its result does not depend on other groups of the
+// wavefront.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void jacobi_onesided(double (&g)[R], double (&v)[R], int j, int gbase,
+                                                uint64_t gmask, bool live, double tol,
+                                                int max_sweeps) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr bool kKeepPartner = R <= 20;
+  bool done = !live;
+#pragma nounroll
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (__ballot(!done) == 0ull) break;
+    bool rot = false;
+#pragma nounroll
+    for (int step = 0; step < NC; ++step) {
+      const bool odd = (step & 1) != 0;
+      const int partner = odd ? ((j & 1) ? j + 1 : j - 1) : (j ^ 1);
+      const bool act = !done && (!odd || (j != 0 && j != NC - 1));
+      const int src = gbase + (act ? partner : j);
+      const bool lower = j < partner;
+      double own2 = 0.0, gam = 0.0;
+      double pg[kKeepPartner ? R : 1];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const double p = __shfl(g[i], src);
+        if constexpr (kKeepPartner) pg[i] = p;
+        own2 = fma(g[i], g[i], own2);
+        gam = fma(g[i], p, gam);
+      }
+      const double par2 = __shfl(own2, src);
+      const double alpha = lower ? own2 : par2;
+      const double beta = lower ? par2 : own2;
+      double cs = 1.0, sn = 0.0;
+      if (act && fabs(gam) > tol * sqrt(alpha * beta)) {
+        const double zeta = (beta - alpha) / (2.0 * gam);
+        double t;
+        if (fabs(zeta) > 1e150)
+          t = 0.5 / zeta;
+        else
+          t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        cs = 1.0 / sqrt(1.0 + t * t);
+        sn = cs * t;
+        rot = true;
+      }
+      // lower position receives y' = s x + c y, upper receives x' = c x - s y
+      const double a_own = lower ? sn : -sn;
+      const double a_par = cs;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        double p;
+        if constexpr (kKeepPartner)
+          p = pg[i];
+        else
+          p = __shfl(g[i], src);
+        const double pv = __shfl(v[i], src);
+        const double ng = fma(a_own, g[i], a_par * p);
+        const double nv = fma(a_own, v[i], a_par * pv);
+        g[i] = act ? ng : g[i];
+        v[i] = act ? nv : v[i];
+      }
+    }
+    if ((__ballot(rot) & gmask) == 0ull) done = true;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-subject R x R algebra of the Procrustes step (objective
+// (procrustes_obj)) in FP64, column per lane.  With A = X_k V, C = A^T A,
+// M = H diag(w), B = A M^T and G = B^T B = M C M^T, the polar factor is
+// Q_k = B G^{-1/2} and
+//     F    = G^{-1/2} M        (so that Q_k = A F^T)
+//     Y V  = Q_k^T A = F C     (the R x R product Y_k V of equation (mttkrp1_3))
+// G^{-1/2} is the pseudo-inverse square root: eigenvalues <= tau * lambda_max
+// are dropped.  Cs is C (R x R, row-major, symmetric) and w the subject's row
+// of W (R doubles), both in the group's LDS; Hs is H (R x R, row-major) in
+// the block's LDS.  On exit lane c (< R) holds F(:, c) in f and (Y V)(:, c)
+// in y.  S is the group's LDS scratch of NC x R doubles, dl of NC doubles.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, const double* Hs,
+                                          double* S, double* dl, int c, int gbase, uint64_t gmask,
+                                          bool live, double tau, double tol, int max_sweeps,
+                                          double (&f)[R], double (&y)[R]) {
+  constexpr int NC = Geo<R>::NC;
+  const bool real = c < R;
+  const int cc = real ? c : 0;
+  // T(c, :) = C(c, :) M^T,   T(c, j) = sum_l C(c, l) w(l) H(j, l)
+  {
+    double cw[R];
+#pragma unroll
+    for (int l = 0; l < R; ++l) cw[l] = Cs[cc * R + l] * w[l];
+#pragma nounroll
+    for (int jj = 0; jj < R; ++jj) {
+      double t = 0.0;
+#pragma unroll
+      for (int l = 0; l < R; ++l) t = fma(Hs[jj * R + l], cw[l], t);
+      if (real) S[c * R + jj] = t;
+    }
+  }
+  wave_sync();
+  // g = G(:, c) = sum_l H(:, l) w(l) T(l, c)
+  double g[R], v[R];
+  {
+    double u[R];
+#pragma unroll
+    for (int l = 0; l < R; ++l) u[l] = real ? w[l] * S[l * R + cc] : 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int l = 0; l < R; ++l) t = fma(Hs[i * R + l], u[l], t);
+      g[i] = t;
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = (i == c) ? 1.0 : 0.0;
+  }
+  wave_sync();
+  jacobi_onesided<R>(g, v, c, gbase, gmask, live, tol, max_sweeps);
+  // eigenvalue at this position and the group's largest one
+  double lam = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) lam = fma(v[i], g[i], lam);
+  dl[c] = lam;
+  wave_sync();
+  double lmax = 0.0;
+  for (int p = 0; p < NC; ++p) lmax = fmax(lmax, dl[p]);
+  wave_sync();
+  const double d = (lam > tau * lmax && lam > 0.0) ? 1.0 / sqrt(lam) : 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) S[c * R + i] = v[i];
+  dl[c] = d;
+  wave_sync();
+  // F(:, c) = sum_p d_p v_p (v_p . M(:, c)),   M(:, c) = H(:, c) w(c)
+  {
+    double m[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) m[i] = Hs[i * R + cc] * w[cc];
+#pragma unroll
+    for (int i = 0; i < R; ++i) f[i] = 0.0;
+#pragma nounroll
+    for (int p = 0; p < NC; ++p) {
+      double z = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) z = fma(S[p * R + i], m[i], z);
+      z *= dl[p];
+#pragma unroll
+      for (int i = 0; i < R; ++i) f[i] = fma(z, S[p * R + i], f[i]);
+    }
+    if (!real) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) f[i] = 0.0;
+    }
+  }
+  wave_sync();
+  // (Y V)(:, c) = sum_l F(:, l) C(l, c)
+  if (real) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) S[c * R + i] = f[i];
+  }
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < R; ++i) y[i] = 0.0;
+#pragma nounroll
+  for (int l = 0; l < R; ++l) {
+    const double cl = Cs[l * R + cc];
+#pragma unroll
+    for (int i = 0; i < R; ++i) y[i] = fma(S[l * R + i], cl, y[i]);
+  }
+  if (!real) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) y[i] = 0.0;
+  }
+  wave_sync();
+}
+
+}  // namespace p2

@@ -1,0 +1,1216 @@
+// HIP kernels of the PARAFAC2-ALS hot path (gfx950) and their launchers.
+//
+// Per-iteration kernel sequence (see p2_capi.hip for the driver):
+//   k_alpha     (first iteration only) gather A_k = X_k V, C_k = A_k^T A_k,
+//               Procrustes polar in FP64, F_k = G_k^{-1/2} H S_k, mode-1
+//               partial (Y_k V) S_k accumulated into M1;
+//   k_gram_tall W^T W;
+//   k_solve_h   H <- M1 ((W^T W) * (V^T V))^+, normalise, prepare N2^+;
+//   k_mode2     regather A_k, D_k = A_k F_k^T H S_k, scatter X_k^T D_k into M2;
+//   k_vupdate / k_gram_tall / k_solve_n3 / k_vscale   V <- M2 N2^+, normalise,
+//               N3 = (V^T V) * (H^T H) and its pseudo-inverse;
+//   k_gamma     regather A_k against V_t and V_{t+1}: mode-3 row
+//               diag(H^T F_k A_k^T A'_k), W row update, fit terms, and the
+//               next iteration's Procrustes step and mode-1 partial from
+//               C'_k = A'_k^T A'_k;
+//   k_fit       fit of the iteration.
+#include "p2_device.h"
+#include "p2_kernels.h"
+
+namespace p2 {
+
+// ---------------------------------------------------------------------------
+// shared helpers
+// ---------------------------------------------------------------------------
+
+struct Lane {
+  int lane;    // lane in wavefront
+  int grp;     // group index in wavefront
+  int j;       // position in group
+  int gbase;   // first lane of the group
+  uint64_t gmask;
+  bool live;   // lane belongs to a group
+};
+
+template <int R>
+__device__ __forceinline__ Lane lane_info() {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int GPW = Geo<R>::GPW;
+  Lane L;
+  L.lane = threadIdx.x & (kWave - 1);
+  L.grp = L.lane / NC;
+  L.live = L.grp < GPW;
+  if (L.live) {
+    L.j = L.lane - L.grp * NC;
+    L.gbase = L.grp * NC;
+    L.gmask = (NC == 64) ? ~0ull : (((1ull << NC) - 1ull) << L.gbase);
+  } else {
+    L.j = 0;
+    L.gbase = L.lane;
+    L.gmask = 0ull;
+  }
+  return L;
+}
+
+__device__ __forceinline__ void block_reduce_atomic(double* sh, int n, double* out) {
+  // sh holds n partial values (already summed in LDS by atomics)
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = sh[i];
+    if (v != 0.0) atomicAdd(out + i, v);
+  }
+}
+
+// per-group LDS regions are carved from one dynamic allocation
+extern __shared__ __align__(16) unsigned char p2_smem[];
+
+// Per-group LDS of the polar kernels (doubles): a region that holds the
+// gather chunks in the first phase and C, F, P and the Jacobi scratch later,
+// then w, a second R-vector and the eigenvalue slots.
+template <int R>
+struct PolarLds {
+  static constexpr int NC = Geo<R>::NC;
+  static constexpr int CH = NC;
+  static constexpr int kA = 2 * CH * R;
+  static constexpr int kB = R * R + NC * R;
+  static constexpr int kRegion = kA > kB ? kA : kB;
+  static constexpr int kPerGroup = kRegion + 2 * R + NC;
+};
+
+template <int R>
+__device__ __forceinline__ void load_shared_rxr(double* dst, const double* __restrict__ src) {
+  for (int i = threadIdx.x; i < R * R; i += blockDim.x) dst[i] = src[i];
+}
+
+// M1 partial of one subject, column c: (Y_k V)(:, c) w(c)  (equation (mttkrp1_3))
+template <int R>
+__device__ __forceinline__ void add_m1(double* shM1, const double (&y)[R], double wc, int c) {
+  if (c < R) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) atomicAdd(&shM1[i * R + c], y[i] * wc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_alpha: first Procrustes step of a run
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ void __launch_bounds__(256) k_alpha(XEnc X, int64_t K, const float* __restrict__ V,
+                                                const float* __restrict__ W,
+                                                const double* __restrict__ H, float* __restrict__ F,
+                                                double* __restrict__ M1, PolarParams pp) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int GPW = Geo<R>::GPW;
+  constexpr int CH = PolarLds<R>::CH;
+  const Lane L = lane_info<R>();
+  const int wave = threadIdx.x / kWave;
+  const int groups_per_block = (blockDim.x / kWave) * GPW;
+  double* Hs = reinterpret_cast<double*>(p2_smem);
+  double* shM1 = Hs + R * R;
+  double* gbuf = shM1 + R * R + (wave * GPW + (L.live ? L.grp : 0)) * PolarLds<R>::kPerGroup;
+  double* region = gbuf;
+  double* Cs = region;
+  double* S = region + R * R;
+  double* wv = gbuf + PolarLds<R>::kRegion;
+  double* dl = wv + 2 * R;
+  load_shared_rxr<R>(Hs, H);
+  for (int i = threadIdx.x; i < R * R; i += blockDim.x) shM1[i] = 0.0;
+  __syncthreads();
+
+  const int c = L.j;
+  if (L.live) {
+    const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
+    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
+    for (int64_t k = gid; k < K; k += stride) {
+      const Subj s = X.subj(k);
+      {
+        double crow[R];
+#pragma unroll
+        for (int l = 0; l < R; ++l) crow[l] = 0.0;
+        for (int i0 = 0; i0 < s.nrows; i0 += CH) {
+          const int n = min(CH, s.nrows - i0);
+          gather_rows<R>(X, s, i0, n, V, region, c);
+          wave_sync();
+          gram_accum<R>(region, region, n, c, crow);
+          wave_sync();
+        }
+        if (c < R) {
+#pragma unroll
+          for (int l = 0; l < R; ++l) Cs[c * R + l] = crow[l];
+          wv[c] = (double)W[k * R + c];
+        }
+      }
+      wave_sync();
+      double f[R], y[R];
+      polar_rxr<R>(Cs, wv, Hs, S, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
+                   pp.max_sweeps, f, y);
+      if (c < R) {
+        float* Fk = F + (size_t)k * R * R + (size_t)c * R;
+#pragma unroll
+        for (int i = 0; i < R; ++i) Fk[i] = (float)f[i];
+        add_m1<R>(shM1, y, wv[c], c);
+      }
+      wave_sync();
+    }
+  }
+  block_reduce_atomic(shM1, R * R, M1);
+}
+
+// ---------------------------------------------------------------------------
+// k_gamma: mode 3 + W update + fit terms (+ next Procrustes step and mode 1)
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ void __launch_bounds__(256) k_gamma(XEnc X, int64_t K, const float* __restrict__ V0,
+                                                const float* __restrict__ V1,
+                                                float* __restrict__ W,
+                                                const double* __restrict__ H,
+                                                const double* __restrict__ N3,
+                                                const double* __restrict__ N3p,
+                                                float* __restrict__ F, float* __restrict__ M3,
+                                                double* __restrict__ M1next,
+                                                double* __restrict__ fitacc, int do_next,
+                                                PolarParams pp) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int GPW = Geo<R>::GPW;
+  constexpr int CH = PolarLds<R>::CH;
+  const Lane L = lane_info<R>();
+  const int wave = threadIdx.x / kWave;
+  const int groups_per_block = (blockDim.x / kWave) * GPW;
+  double* Hs = reinterpret_cast<double*>(p2_smem);
+  double* N3s = Hs + R * R;
+  double* N3ps = N3s + R * R;
+  double* shM1 = N3ps + R * R;
+  double* shFit = shM1 + R * R;
+  double* gbuf = shFit + 2 + (wave * GPW + (L.live ? L.grp : 0)) * PolarLds<R>::kPerGroup;
+  double* region = gbuf;
+  double* A0 = region;
+  double* A1 = region + CH * R;
+  double* SF = region;          // F column-major (SF[col * R + row]), later C'
+  double* SP = region + R * R;  // P rows, later the Jacobi scratch
+  double* wv = gbuf + PolarLds<R>::kRegion;
+  double* mv = wv + R;
+  double* dl = mv + R;
+  load_shared_rxr<R>(Hs, H);
+  load_shared_rxr<R>(N3s, N3);
+  load_shared_rxr<R>(N3ps, N3p);
+  for (int i = threadIdx.x; i < R * R + 2; i += blockDim.x) shM1[i] = 0.0;
+  __syncthreads();
+
+  const int c = L.j;
+  const bool real = c < R;
+  const int cc = real ? c : 0;
+  double fa = 0.0, fb = 0.0;
+
+  if (L.live) {
+    const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
+    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
+    for (int64_t k = gid; k < K; k += stride) {
+      const Subj s = X.subj(k);
+      double crow[R];
+      {
+        double prow[R];
+#pragma unroll
+        for (int l = 0; l < R; ++l) prow[l] = crow[l] = 0.0;
+        for (int i0 = 0; i0 < s.nrows; i0 += CH) {
+          const int n = min(CH, s.nrows - i0);
+          gather_rows2<R>(X, s, i0, n, V0, V1, A0, A1, c);
+          wave_sync();
+          gram_accum<R>(A0, A1, n, c, prow);  // row c of P = A^T A'
+          gram_accum<R>(A1, A1, n, c, crow);  // row c of C' = A'^T A'
+          wave_sync();
+        }
+        // F into LDS (column c), P row c into LDS
+        if (real) {
+          const float* Fk = F + (size_t)k * R * R + (size_t)c * R;
+#pragma unroll
+          for (int i = 0; i < R; ++i) SF[c * R + i] = (double)Fk[i];
+#pragma unroll
+          for (int l = 0; l < R; ++l) SP[c * R + l] = prow[l];
+        }
+      }
+      wave_sync();
+      // (Y V')(:, c) = F P(:, c);  m3(c) = H(:, c) . (Y V')(:, c)  (mttkrp3_row_wise)
+      double m3 = 0.0;
+      {
+        double yv[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) yv[i] = 0.0;
+#pragma nounroll
+        for (int l = 0; l < R; ++l) {
+          const double plc = SP[l * R + cc];
+#pragma unroll
+          for (int i = 0; i < R; ++i) yv[i] = fma(SF[l * R + i], plc, yv[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) m3 = fma(Hs[i * R + cc], yv[i], m3);
+      }
+      if (real) mv[c] = m3;
+      wave_sync();
+      // w_new(c) = sum_l m3(l) N3^+(l, c)
+      double wn = 0.0;
+#pragma unroll
+      for (int l = 0; l < R; ++l) wn = fma(mv[l], N3ps[l * R + cc], wn);
+      if (real) {
+        W[k * R + c] = (float)wn;
+        M3[k * R + c] = (float)m3;
+        wv[c] = (double)(float)wn;
+      }
+      wave_sync();
+      if (real) {
+        // loss terms <w, m3> and w^T N3 w, with w as stored
+        const double wf = wv[c];
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < R; ++l) t = fma(N3s[c * R + l], wv[l], t);
+        fa = fma(wf, m3, fa);
+        fb = fma(wf, t, fb);
+      }
+      if (do_next) {
+        // next Procrustes step from C' (stored over F) with H_{t+1} and w_{t+1}
+        if (real) {
+#pragma unroll
+          for (int l = 0; l < R; ++l) SF[c * R + l] = crow[l];
+        }
+        wave_sync();
+        double f[R], y[R];
+        polar_rxr<R>(SF, wv, Hs, SP, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
+                     pp.max_sweeps, f, y);
+        if (real) {
+          float* Fk = F + (size_t)k * R * R + (size_t)c * R;
+#pragma unroll
+          for (int i = 0; i < R; ++i) Fk[i] = (float)f[i];
+          add_m1<R>(shM1, y, wv[c], c);
+        }
+      }
+      wave_sync();
+    }
+  }
+  if (L.live && real) {
+    atomicAdd(&shFit[0], fa);
+    atomicAdd(&shFit[1], fb);
+  }
+  __syncthreads();
+  if (do_next) {
+    for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
+      const double v = shM1[i];
+      if (v != 0.0) atomicAdd(M1next + i, v);
+    }
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(fitacc + 0, shFit[0]);
+    atomicAdd(fitacc + 1, shFit[1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_mode2: M2 += X_k^T (A_k E_k),  E_k = F_k^T H S_k  (equation (mttkrp2_3))
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ void __launch_bounds__(256) k_mode2(XEnc X, int64_t K, const float* __restrict__ V,
+                                                const float* __restrict__ W,
+                                                const double* __restrict__ H,
+                                                const float* __restrict__ F,
+                                                float* __restrict__ M2, int hot) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int GPW = Geo<R>::GPW;
+  constexpr int LDV = Geo<R>::LDV;
+  constexpr int CH = NC;
+  const Lane L = lane_info<R>();
+  const int wave = threadIdx.x / kWave;
+  const int groups_per_block = (blockDim.x / kWave) * GPW;
+  float* shM2 = reinterpret_cast<float*>(p2_smem);  // hot x LDV
+  float* gbuf = shM2 + (size_t)hot * LDV + (wave * GPW + (L.live ? L.grp : 0)) * (CH * R);
+  for (int i = threadIdx.x; i < hot * LDV; i += blockDim.x) shM2[i] = 0.f;
+  __syncthreads();
+
+  const int c = L.j;
+  const bool real = c < R;
+  const int cc = real ? c : 0;
+  if (L.live) {
+    float hc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) hc[i] = (float)H[i * R + cc];
+    const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
+    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
+    for (int64_t k = gid; k < K; k += stride) {
+      const Subj s = X.subj(k);
+      // E(:, c) = w(c) F^T H(:, c)
+      float e[R];
+      {
+        const float* Fk = F + (size_t)k * R * R;
+        const float wc = W[k * R + cc];
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+          float t = 0.f;
+#pragma unroll
+          for (int i = 0; i < R; ++i) t = fmaf(Fk[p * R + i], hc[i], t);
+          e[p] = t * wc;
+        }
+      }
+      for (int i0 = 0; i0 < s.nrows; i0 += CH) {
+        const int n = min(CH, s.nrows - i0);
+        gather_rows<R>(X, s, i0, n, V, gbuf, c);
+        wave_sync();
+        int zs, ze;
+        X.row(s, i0, zs, ze);
+        for (int ii = 0; ii < n; ++ii) {
+          float d = 0.f;
+#pragma unroll
+          for (int p = 0; p < R; ++p) d = fmaf(gbuf[ii * R + p], e[p], d);
+          if (ii > 0) X.row(s, i0 + ii, zs, ze);
+          for (int z = zs; z < ze; ++z) {
+            const int j = X.colat(s, z);
+            const float v = X.valat(s, z) * d;
+            if (real) {
+              if (j < hot)
+                atomicAdd(&shM2[j * LDV + c], v);
+              else
+                atomicAdd(&M2[(size_t)j * LDV + c], v);
+            }
+          }
+        }
+        wave_sync();
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < hot * LDV; i += blockDim.x) {
+    const float v = shM2[i];
+    if (v != 0.f) atomicAdd(&M2[i], v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tall-skinny Gram out(R x R, FP64) += A^T A for A (n x R, FP32, row stride lda)
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ void __launch_bounds__(256) k_gram_tall(const float* __restrict__ A, int64_t n,
+                                                    int lda, double* __restrict__ out) {
+  constexpr int GPW = Geo<R>::GPW;
+  const Lane L = lane_info<R>();
+  const int wave = threadIdx.x / kWave;
+  const int groups_per_block = (blockDim.x / kWave) * GPW;
+  double* sh = reinterpret_cast<double*>(p2_smem);
+  for (int i = threadIdx.x; i < R * R; i += blockDim.x) sh[i] = 0.0;
+  __syncthreads();
+  const int c = L.j;
+  if (L.live && c < R) {
+    double acc[R];
+#pragma unroll
+    for (int l = 0; l < R; ++l) acc[l] = 0.0;
+    const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
+    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
+    for (int64_t r = gid; r < n; r += stride) {
+      const float* a = A + r * lda;
+      const double ac = (double)a[c];
+#pragma unroll
+      for (int l = 0; l < R; ++l) acc[l] = fma(ac, (double)a[l], acc[l]);
+    }
+#pragma unroll
+    for (int l = 0; l < R; ++l)
+      if (acc[l] != 0.0) atomicAdd(&sh[c * R + l], acc[l]);
+  }
+  block_reduce_atomic(sh, R * R, out);
+}
+
+// ---------------------------------------------------------------------------
+// small FP64 solves (one group of NC lanes)
+// ---------------------------------------------------------------------------
+
+// Column c of N^+ for symmetric PSD N given column-per-lane (n = N(:, c)).
+template <int R>
+__device__ void pinv_cols(const double (&ncol)[R], int c, double* S, double* dl, double tau,
+                          double tol, int max_sweeps, double (&out)[R]) {
+  constexpr int NC = Geo<R>::NC;
+  double g[R], v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    g[i] = (c < R) ? ncol[i] : 0.0;
+    v[i] = (i == c) ? 1.0 : 0.0;
+  }
+  const uint64_t gmask = (NC == 64) ? ~0ull : ((1ull << NC) - 1ull);
+  jacobi_onesided<R>(g, v, c, 0, gmask, c < NC, tol, max_sweeps);
+  double lam = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) lam = fma(v[i], g[i], lam);
+  if (c < NC) dl[c] = lam;
+  __syncthreads();
+  double lmax = 0.0;
+  for (int p = 0; p < NC; ++p) lmax = fmax(lmax, dl[p]);
+  __syncthreads();
+  const double inv = (lam > tau * lmax && lam > 0.0) ? 1.0 / lam : 0.0;
+  if (c < NC) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) S[c * R + i] = v[i];
+    dl[c] = inv;
+  }
+  __syncthreads();
+  const int cc = c < R ? c : 0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) out[i] = 0.0;
+  for (int p = 0; p < NC; ++p) {
+    const double z = S[p * R + cc] * dl[p];
+#pragma unroll
+    for (int i = 0; i < R; ++i) out[i] = fma(z, S[p * R + i], out[i]);
+  }
+  __syncthreads();
+}
+
+// H <- M1 ((W^T W) * (V^T V))^+ (Algorithm "CP-ALS"), unit columns; H^T H;
+// N2^+ = ((W^T W) * (H^T H))^+.
+template <int R>
+__global__ void __launch_bounds__(64) k_solve_h(const double* __restrict__ M1,
+                                                 const double* __restrict__ WtW,
+                                                 const double* __restrict__ VtV,
+                                                 double* __restrict__ H, double* __restrict__ HtH,
+                                                 double* __restrict__ N2p, PolarParams pp) {
+  constexpr int NC = Geo<R>::NC;
+  __shared__ double S[NC * R];
+  __shared__ double dl[NC];
+  __shared__ double Hs[R * R];
+  const int c = threadIdx.x;
+  const int cc = c < R ? c : 0;
+  double ncol[R], np[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) ncol[i] = WtW[i * R + cc] * VtV[i * R + cc];
+  pinv_cols<R>(ncol, c, S, dl, pp.tau_pinv, pp.tol, pp.max_sweeps, np);
+  // column c of H = M1 N1^+
+  double h[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < R; ++l) t = fma(M1[i * R + l], np[l], t);
+    h[i] = t;
+  }
+  double nrm = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) nrm = fma(h[i], h[i], nrm);
+  nrm = sqrt(nrm);
+  const double sc = nrm > 1e-300 ? 1.0 / nrm : 1.0;
+  if (c < R) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      h[i] *= sc;
+      Hs[i * R + c] = h[i];
+      H[i * R + c] = h[i];
+    }
+  }
+  __syncthreads();
+  // column c of H^T H and of N2 = (W^T W) * (H^T H)
+#pragma unroll
+  for (int l = 0; l < R; ++l) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) t = fma(Hs[i * R + l], Hs[i * R + cc], t);
+    if (c < R) HtH[l * R + c] = t;
+    ncol[l] = WtW[l * R + cc] * t;
+  }
+  pinv_cols<R>(ncol, c, S, dl, pp.tau_pinv, pp.tol, pp.max_sweeps, np);
+  if (c < R) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) N2p[i * R + c] = np[i];
+  }
+}
+
+// V_raw(j, :) = M2(j, :) N2^+  (rows of stride LDV; padding stays zero)
+template <int R>
+__global__ void __launch_bounds__(256) k_vupdate(const float* __restrict__ M2,
+                                                  const double* __restrict__ N2p, int64_t J,
+                                                  float* __restrict__ Vout) {
+  constexpr int LDV = Geo<R>::LDV;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < J;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    double m[R];
+#pragma unroll
+    for (int l = 0; l < R; ++l) m[l] = (double)M2[j * LDV + l];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      double t = 0.0;
+#pragma unroll
+      for (int l = 0; l < R; ++l) t = fma(m[l], N2p[l * R + c], t);
+      Vout[j * LDV + c] = (float)t;
+    }
+  }
+}
+
+// Column norms of V_raw from its Gram, V^T V of the normalised V,
+// N3 = (V^T V) * (H^T H) and N3^+.
+template <int R>
+__global__ void __launch_bounds__(64) k_solve_n3(const double* __restrict__ VtVraw,
+                                                  const double* __restrict__ HtH,
+                                                  double* __restrict__ VtV,
+                                                  double* __restrict__ invnorm,
+                                                  double* __restrict__ N3,
+                                                  double* __restrict__ N3p, PolarParams pp) {
+  constexpr int NC = Geo<R>::NC;
+  __shared__ double S[NC * R];
+  __shared__ double dl[NC];
+  __shared__ double inv[R];
+  const int c = threadIdx.x;
+  const int cc = c < R ? c : 0;
+  if (c < R) {
+    const double n2 = VtVraw[c * R + c];
+    const double nrm = sqrt(n2);
+    inv[c] = nrm > 1e-300 ? 1.0 / nrm : 1.0;
+    invnorm[c] = inv[c];
+  }
+  __syncthreads();
+  double ncol[R], np[R];
+#pragma unroll
+  for (int l = 0; l < R; ++l) {
+    const double vtv = VtVraw[l * R + cc] * inv[l] * inv[cc];
+    if (c < R) {
+      VtV[l * R + c] = vtv;
+      N3[l * R + c] = vtv * HtH[l * R + c];
+    }
+    ncol[l] = vtv * HtH[l * R + cc];
+  }
+  pinv_cols<R>(ncol, c, S, dl, pp.tau_pinv, pp.tol, pp.max_sweeps, np);
+  if (c < R) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) N3p[i * R + c] = np[i];
+  }
+}
+
+template <int R>
+__global__ void __launch_bounds__(256) k_vscale(float* __restrict__ Vv, int64_t J,
+                                                 const double* __restrict__ invnorm) {
+  constexpr int LDV = Geo<R>::LDV;
+  const int64_t n = J * LDV;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t % LDV);
+    if (c < R) Vv[t] = (float)((double)Vv[t] * invnorm[c]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Q_k = A_k F_k^T for subjects [k0, k1): rows written contiguously from Q.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ void __launch_bounds__(256) k_getq(XEnc X, int64_t k0, int64_t k1,
+                                               const float* __restrict__ V,
+                                               const float* __restrict__ F, float* __restrict__ Q,
+                                               int64_t row0) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int GPW = Geo<R>::GPW;
+  constexpr int CH = NC;
+  const Lane L = lane_info<R>();
+  const int wave = threadIdx.x / kWave;
+  const int groups_per_block = (blockDim.x / kWave) * GPW;
+  float* gbuf = reinterpret_cast<float*>(p2_smem) + (wave * GPW + (L.live ? L.grp : 0)) * (CH * R);
+  if (!L.live) return;
+  const int c = L.j;
+  const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
+  const int64_t stride = (int64_t)gridDim.x * groups_per_block;
+  for (int64_t k = k0 + gid; k < k1; k += stride) {
+    const Subj s = X.subj(k);
+    float fr[R];  // row c of F^T = column c of F ... Q(i, c) = sum_p A(i, p) F(c, p)
+    const float* Fk = F + (size_t)k * R * R;
+    const int cc = c < R ? c : 0;
+#pragma unroll
+    for (int p = 0; p < R; ++p) fr[p] = Fk[p * R + cc];
+    for (int i0 = 0; i0 < s.nrows; i0 += CH) {
+      const int n = min(CH, s.nrows - i0);
+      gather_rows<R>(X, s, i0, n, V, gbuf, c);
+      wave_sync();
+      if (c < R) {
+        for (int ii = 0; ii < n; ++ii) {
+          float t = 0.f;
+#pragma unroll
+          for (int p = 0; p < R; ++p) t = fmaf(gbuf[ii * R + p], fr[p], t);
+          Q[(s.r0 - row0 + i0 + ii) * R + c] = t;
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// projection of new subjects onto fixed (V, H): n_steps alternations of the
+// Procrustes step and the least-squares update of w (plain CSR input)
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float* __restrict__ V,
+                                                  const double* __restrict__ H,
+                                                  const double* __restrict__ N3,
+                                                  const double* __restrict__ N3p, int n_steps,
+                                                  const float* __restrict__ w0,
+                                                  float* __restrict__ Qout,
+                                                  float* __restrict__ wout,
+                                                  double* __restrict__ lossout, PolarParams pp) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int GPW = Geo<R>::GPW;
+  constexpr int CH = PolarLds<R>::CH;
+  const Lane L = lane_info<R>();
+  const int wave = threadIdx.x / kWave;
+  const int groups_per_block = (blockDim.x / kWave) * GPW;
+  double* Hs = reinterpret_cast<double*>(p2_smem);
+  double* N3s = Hs + R * R;
+  double* N3ps = N3s + R * R;
+  double* gbuf = N3ps + R * R + (wave * GPW + (L.live ? L.grp : 0)) * PolarLds<R>::kPerGroup;
+  double* region = gbuf;
+  double* Cs = region;
+  double* S = region + R * R;
+  double* wv = gbuf + PolarLds<R>::kRegion;
+  double* mv = wv + R;
+  double* dl = mv + R;
+  load_shared_rxr<R>(Hs, H);
+  load_shared_rxr<R>(N3s, N3);
+  load_shared_rxr<R>(N3ps, N3p);
+  __syncthreads();
+  if (!L.live) return;
+  const int c = L.j;
+  const bool real = c < R;
+  const int cc = real ? c : 0;
+  const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
+  const int64_t stride = (int64_t)gridDim.x * groups_per_block;
+  for (int64_t k = gid; k < K; k += stride) {
+    const Subj s = X.subj(k);
+    {
+      double crow[R];
+#pragma unroll
+      for (int l = 0; l < R; ++l) crow[l] = 0.0;
+      for (int i0 = 0; i0 < s.nrows; i0 += CH) {
+        const int n = min(CH, s.nrows - i0);
+        gather_rows<R>(X, s, i0, n, V, region, c);
+        wave_sync();
+        gram_accum<R>(region, region, n, c, crow);
+        wave_sync();
+      }
+      if (real) {
+#pragma unroll
+        for (int l = 0; l < R; ++l) Cs[c * R + l] = crow[l];
+        wv[c] = w0 ? (double)w0[k * R + c] : 1.0;
+      }
+    }
+    double xx = 0.0;  // ||X_k||^2, summed by lane 0 of the group
+    if (c == 0) {
+      for (int z = 0; z < s.nnz; ++z) {
+        const double x = (double)X.val[s.z0 + z];
+        xx = fma(x, x, xx);
+      }
+    }
+    wave_sync();
+    double f[R], y[R], m3 = 0.0;
+#pragma nounroll
+    for (int step = 0; step < n_steps; ++step) {
+      polar_rxr<R>(Cs, wv, Hs, S, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
+                   pp.max_sweeps, f, y);
+      m3 = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) m3 = fma(Hs[i * R + cc], y[i], m3);
+      if (real) mv[c] = m3;
+      wave_sync();
+      double wn = 0.0;
+#pragma unroll
+      for (int l = 0; l < R; ++l) wn = fma(mv[l], N3ps[l * R + cc], wn);
+      wave_sync();
+      if (real) wv[c] = wn;
+      wave_sync();
+    }
+    // outputs: w, loss = ||X||^2 - 2 <w, m3> + w^T N3 w, Q = A F^T
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < R; ++l) t = fma(N3s[cc * R + l], wv[l], t);
+    const double part = real ? (-2.0 * wv[c] * m3 + wv[c] * t) : 0.0;
+    if (real) wout[k * R + c] = (float)wv[c];
+    wave_sync();
+    if (real) mv[c] = part;
+    wave_sync();
+    if (c == 0 && lossout) {
+      double loss = xx;
+      for (int l = 0; l < R; ++l) loss += mv[l];
+      lossout[k] = loss;
+    }
+    wave_sync();
+    if (Qout) {
+      // Q = A F^T:  Q(i, c) = sum_p A(i, p) F(c, p); F(c, p) is element c of lane p's f
+      if (real) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) S[c * R + i] = f[i];
+      }
+      wave_sync();
+      float fr[R];
+#pragma unroll
+      for (int p = 0; p < R; ++p) fr[p] = (float)S[p * R + cc];
+      wave_sync();
+      float* Ab = reinterpret_cast<float*>(region);
+      for (int i0 = 0; i0 < s.nrows; i0 += CH) {
+        const int n = min(CH, s.nrows - i0);
+        gather_rows<R>(X, s, i0, n, V, Ab, c);
+        wave_sync();
+        if (real) {
+          for (int ii = 0; ii < n; ++ii) {
+            float q = 0.f;
+#pragma unroll
+            for (int p = 0; p < R; ++p) q = fmaf(Ab[ii * R + p], fr[p], q);
+            Qout[(s.r0 + i0 + ii) * R + c] = q;
+          }
+        }
+        wave_sync();
+      }
+    }
+    wave_sync();
+  }
+}
+
+// N3 = (V^T V) * (H^T H) and N3^+ for a projection model with fixed V and H.
+template <int R>
+__global__ void __launch_bounds__(64) k_model_prep(const double* __restrict__ VtV,
+                                                    const double* __restrict__ H,
+                                                    double* __restrict__ HtH,
+                                                    double* __restrict__ N3,
+                                                    double* __restrict__ N3p, PolarParams pp) {
+  constexpr int NC = Geo<R>::NC;
+  __shared__ double S[NC * R];
+  __shared__ double dl[NC];
+  const int c = threadIdx.x;
+  const int cc = c < R ? c : 0;
+  double ncol[R], np[R];
+#pragma unroll
+  for (int l = 0; l < R; ++l) {
+    double t = 0.0;
+    for (int i = 0; i < R; ++i) t = fma(H[i * R + l], H[i * R + cc], t);
+    if (c < R) {
+      HtH[l * R + c] = t;
+      N3[l * R + c] = VtV[l * R + c] * t;
+    }
+    ncol[l] = VtV[l * R + cc] * t;
+  }
+  pinv_cols<R>(ncol, c, S, dl, pp.tau_pinv, pp.tol, pp.max_sweeps, np);
+  if (c < R) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) N3p[i * R + c] = np[i];
+  }
+}
+
+__global__ void k_iota(int32_t* __restrict__ p, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = (int32_t)t;
+}
+
+// ---------------------------------------------------------------------------
+// init-time kernels (encoding, validation, statistics)
+// ---------------------------------------------------------------------------
+
+__global__ void k_validate_rows(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                const float* __restrict__ val, int64_t n_rows, int64_t nnz,
+                                int64_t J, int* __restrict__ err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = row_ptr[i], b = row_ptr[i + 1];
+    if (a < 0 || b < a || b > nnz) {
+      atomicOr(err, 1);
+      continue;
+    }
+    int prev = -1;
+    for (int64_t z = a; z < b; ++z) {
+      const int cz = col[z];
+      if (cz < 0 || cz >= J) atomicOr(err, 2);
+      if (cz <= prev) atomicOr(err, 4);
+      prev = cz;
+      if (!isfinite(val[z])) atomicOr(err, 8);
+    }
+  }
+}
+
+__global__ void k_validate_subj(const int64_t* __restrict__ subj_ptr,
+                                const int64_t* __restrict__ row_ptr, int64_t K, int64_t n_rows,
+                                int R, int* __restrict__ err, int64_t* __restrict__ zbase,
+                                int64_t* __restrict__ rbase) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= K;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = subj_ptr[k];
+    if (r < 0 || r > n_rows) {
+      atomicOr(err, 16);
+      continue;
+    }
+    rbase[k] = r;
+    zbase[k] = row_ptr[r];
+    if (k < K) {
+      const int64_t r1 = subj_ptr[k + 1];
+      if (r1 < r || r1 > n_rows) {
+        atomicOr(err, 16);
+        continue;
+      }
+      const int64_t I = r1 - r;
+      if (I < R) atomicOr(err, 32);
+      if (I > 65535) atomicOr(err, 64);
+      if (r1 <= n_rows && row_ptr[r1] - row_ptr[r] > 65535) atomicOr(err, 128);
+    }
+  }
+}
+
+__global__ void k_encode_rows(const int64_t* __restrict__ subj_ptr,
+                              const int64_t* __restrict__ row_ptr, int64_t K,
+                              uint16_t* __restrict__ rstart) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r0 = subj_ptr[k], r1 = subj_ptr[k + 1];
+    const int64_t z0 = row_ptr[r0];
+    for (int64_t i = r0; i < r1; ++i) rstart[i] = (uint16_t)(row_ptr[i] - z0);
+  }
+}
+
+__global__ void k_col_hist(const int32_t* __restrict__ col, int64_t nnz,
+                           unsigned int* __restrict__ hist) {
+  for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < nnz;
+       z += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[col[z]], 1u);
+}
+
+__global__ void k_encode_cols(const int32_t* __restrict__ col, const float* __restrict__ val,
+                              int64_t nnz, const int32_t* __restrict__ rank,
+                              uint16_t* __restrict__ col16, float* __restrict__ val_out,
+                              double* __restrict__ nx2) {
+  double acc = 0.0;
+  for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < nnz;
+       z += (int64_t)gridDim.x * blockDim.x) {
+    col16[z] = (uint16_t)rank[col[z]];
+    const float v = val[z];
+    val_out[z] = v;
+    acc = fma((double)v, (double)v, acc);
+  }
+  // wave reduction, then one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0 && acc != 0.0) atomicAdd(nx2, acc);
+}
+
+// Vint(rank[j], :) = V(j, :)  or the inverse when to_user != 0
+__global__ void k_permute_rows(const float* __restrict__ src, float* __restrict__ dst, int64_t J,
+                               int R, int ld_src, int ld_dst, const int32_t* __restrict__ map) {
+  const int64_t n = J * R;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / R;
+    const int c = (int)(t % R);
+    dst[(int64_t)map[j] * ld_dst + c] = src[j * ld_src + c];
+  }
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+__global__ void k_fit(const double* __restrict__ fitacc, const double* __restrict__ nx2,
+                      double* __restrict__ fit_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double loss = nx2[0] - 2.0 * fitacc[0] + fitacc[1];
+    fit_out[0] = 1.0 - loss / nx2[0];
+  }
+}
+
+}  // namespace p2
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+namespace p2 {
+
+namespace {
+
+constexpr int kMaxBlocks = 2048;
+constexpr int kLdsPerCu = 160 * 1024;
+
+template <int R>
+constexpr int block_threads() {
+  return R >= 32 ? 128 : 256;
+}
+
+inline int grid_for(int64_t units, int per_block) {
+  int64_t b = (units + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > kMaxBlocks) b = kMaxBlocks;
+  return (int)b;
+}
+
+template <class Kern>
+hipError_t allow_lds(Kern k, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+#define P2_RANKS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(32) X(40)
+
+#define P2_DISPATCH(R, CALL)            \
+  switch (R) {                          \
+    case 1: { constexpr int RR = 1; CALL; } \
+    case 2: { constexpr int RR = 2; CALL; } \
+    case 3: { constexpr int RR = 3; CALL; } \
+    case 4: { constexpr int RR = 4; CALL; } \
+    case 5: { constexpr int RR = 5; CALL; } \
+    case 6: { constexpr int RR = 6; CALL; } \
+    case 8: { constexpr int RR = 8; CALL; } \
+    case 10: { constexpr int RR = 10; CALL; } \
+    case 12: { constexpr int RR = 12; CALL; } \
+    case 16: { constexpr int RR = 16; CALL; } \
+    case 20: { constexpr int RR = 20; CALL; } \
+    case 32: { constexpr int RR = 32; CALL; } \
+    case 40: { constexpr int RR = 40; CALL; } \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <int R>
+hipError_t alpha_t(const XEnc& X, int64_t K, const float* V, const float* W, const double* H,
+                   float* F, double* M1, const PolarParams& pp, hipStream_t s) {
+  constexpr int T = block_threads<R>();
+  const int gpb = (T / kWave) * Geo<R>::GPW;
+  const size_t lds = sizeof(double) * (2 * R * R + (size_t)gpb * PolarLds<R>::kPerGroup);
+  hipError_t e = allow_lds(k_alpha<R>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_alpha<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V, W, H, F, M1,
+                     pp);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t gamma_t(const XEnc& X, int64_t K, const float* V0, const float* V1, float* W,
+                   const double* H, const double* N3, const double* N3p, float* F, float* M3,
+                   double* M1next, double* fitacc, int do_next, const PolarParams& pp,
+                   hipStream_t s) {
+  constexpr int T = block_threads<R>();
+  const int gpb = (T / kWave) * Geo<R>::GPW;
+  const size_t lds = sizeof(double) * (4 * R * R + 2 + (size_t)gpb * PolarLds<R>::kPerGroup);
+  hipError_t e = allow_lds(k_gamma<R>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gamma<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V0, V1, W, H, N3,
+                     N3p, F, M3, M1next, fitacc, do_next, pp);
+  return hipGetLastError();
+}
+
+template <int R>
+int mode2_group_floats() {
+  constexpr int T = block_threads<R>();
+  return (T / kWave) * Geo<R>::GPW * Geo<R>::NC * R;
+}
+
+template <int R>
+int max_hot_t() {
+  // leave room for two resident blocks per CU
+  const int budget = kLdsPerCu / 2 - mode2_group_floats<R>() * 4 - 1024;
+  return budget / (Geo<R>::LDV * 4);
+}
+
+template <int R>
+hipError_t mode2_t(const XEnc& X, int64_t K, const float* V, const float* W, const double* H,
+                   const float* F, float* M2, int hot, hipStream_t s) {
+  constexpr int T = block_threads<R>();
+  const int gpb = (T / kWave) * Geo<R>::GPW;
+  const size_t lds = sizeof(float) * ((size_t)hot * Geo<R>::LDV + mode2_group_floats<R>());
+  hipError_t e = allow_lds(k_mode2<R>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mode2<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V, W, H, F, M2,
+                     hot);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t gram_tall_t(const float* A, int64_t n, int lda, double* out, hipStream_t s) {
+  constexpr int T = 256;
+  const int gpb = (T / kWave) * Geo<R>::GPW;
+  int blocks = grid_for(n, gpb * 16);
+  hipLaunchKernelGGL(k_gram_tall<R>, dim3(blocks), dim3(T), sizeof(double) * R * R, s, A, n, lda,
+                     out);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t getq_t(const XEnc& X, int64_t k0, int64_t k1, const float* V, const float* F, float* Q,
+                  int64_t row0, hipStream_t s) {
+  constexpr int T = block_threads<R>();
+  const int gpb = (T / kWave) * Geo<R>::GPW;
+  const size_t lds = sizeof(float) * (size_t)gpb * Geo<R>::NC * R;
+  hipLaunchKernelGGL(k_getq<R>, dim3(grid_for(k1 - k0, gpb)), dim3(T), lds, s, X, k0, k1, V, F, Q,
+                     row0);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t project_t(const XRaw& X, int64_t K, const float* V, const double* H, const double* N3,
+                     const double* N3p, int n_steps, const float* w0, float* Qout, float* wout,
+                     double* lossout, const PolarParams& pp, hipStream_t s) {
+  constexpr int T = block_threads<R>();
+  const int gpb = (T / kWave) * Geo<R>::GPW;
+  const size_t lds = sizeof(double) * (3 * R * R + (size_t)gpb * PolarLds<R>::kPerGroup);
+  hipError_t e = allow_lds(k_project<R>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_project<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V, H, N3, N3p,
+                     n_steps, w0, Qout, wout, lossout, pp);
+  return hipGetLastError();
+}
+
+inline int grid1(int64_t n, int T = 256) {
+  int64_t b = (n + T - 1) / T;
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (int)b;
+}
+
+}  // namespace
+
+bool rank_supported(int R) {
+  switch (R) {
+#define P2_CASE(r) case r:
+    P2_RANKS(P2_CASE)
+#undef P2_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+int lds_bytes_per_cu() { return kLdsPerCu; }
+
+int mode2_max_hot(int R) {
+  switch (R) {
+#define P2_CASE(r) \
+  case r:          \
+    return max_hot_t<r>();
+    P2_RANKS(P2_CASE)
+#undef P2_CASE
+    default:
+      return 0;
+  }
+}
+
+hipError_t run_alpha(int R, const XEnc& X, int64_t K, const float* V, const float* W,
+                     const double* H, float* F, double* M1, const PolarParams& pp,
+                     hipStream_t s) {
+  P2_DISPATCH(R, return alpha_t<RR>(X, K, V, W, H, F, M1, pp, s))
+}
+
+hipError_t run_gamma(int R, const XEnc& X, int64_t K, const float* V0, const float* V1, float* W,
+                     const double* H, const double* N3, const double* N3p, float* F, float* M3,
+                     double* M1next, double* fitacc, int do_next, const PolarParams& pp,
+                     hipStream_t s) {
+  P2_DISPATCH(R, return gamma_t<RR>(X, K, V0, V1, W, H, N3, N3p, F, M3, M1next, fitacc, do_next,
+                                    pp, s))
+}
+
+hipError_t run_mode2(int R, const XEnc& X, int64_t K, const float* V, const float* W,
+                     const double* H, const float* F, float* M2, int hot, hipStream_t s) {
+  P2_DISPATCH(R, return mode2_t<RR>(X, K, V, W, H, F, M2, hot, s))
+}
+
+hipError_t run_gram_tall(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s) {
+  P2_DISPATCH(R, return gram_tall_t<RR>(A, n, lda, out, s))
+}
+
+hipError_t run_solve_h(int R, const double* M1, const double* WtW, const double* VtV, double* H,
+                       double* HtH, double* N2p, const PolarParams& pp, hipStream_t s) {
+  P2_DISPATCH(R, hipLaunchKernelGGL(k_solve_h<RR>, dim3(1), dim3(64), 0, s, M1, WtW, VtV, H, HtH,
+                                    N2p, pp);
+              return hipGetLastError())
+}
+
+hipError_t run_vupdate(int R, const float* M2, const double* N2p, int64_t J, float* Vout,
+                       hipStream_t s) {
+  P2_DISPATCH(R, hipLaunchKernelGGL(k_vupdate<RR>, dim3(grid1(J)), dim3(256), 0, s, M2, N2p, J,
+                                    Vout);
+              return hipGetLastError())
+}
+
+hipError_t run_solve_n3(int R, const double* VtVraw, const double* HtH, double* VtV,
+                        double* invnorm, double* N3, double* N3p, const PolarParams& pp,
+                        hipStream_t s) {
+  P2_DISPATCH(R, hipLaunchKernelGGL(k_solve_n3<RR>, dim3(1), dim3(64), 0, s, VtVraw, HtH, VtV,
+                                    invnorm, N3, N3p, pp);
+              return hipGetLastError())
+}
+
+hipError_t run_vscale(int R, float* V, int64_t J, const double* invnorm, hipStream_t s) {
+  P2_DISPATCH(R, hipLaunchKernelGGL(k_vscale<RR>, dim3(grid1(J * Geo<RR>::LDV)), dim3(256), 0, s,
+                                    V, J, invnorm);
+              return hipGetLastError())
+}
+
+hipError_t run_getq(int R, const XEnc& X, int64_t k0, int64_t k1, const float* V, const float* F,
+                    float* Q, int64_t row0, hipStream_t s) {
+  P2_DISPATCH(R, return getq_t<RR>(X, k0, k1, V, F, Q, row0, s))
+}
+
+hipError_t run_project(int R, const XRaw& X, int64_t K, const float* V, const double* H,
+                       const double* N3, const double* N3p, int n_steps, const float* w0,
+                       float* Qout, float* wout, double* lossout, const PolarParams& pp,
+                       hipStream_t s) {
+  P2_DISPATCH(R, return project_t<RR>(X, K, V, H, N3, N3p, n_steps, w0, Qout, wout, lossout, pp,
+                                      s))
+}
+
+hipError_t run_validate(const int64_t* subj_ptr, const int64_t* row_ptr, const int32_t* col,
+                        const float* val, int64_t K, int64_t n_rows, int64_t nnz, int64_t J,
+                        int R, int* err, int64_t* zbase, int64_t* rbase, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate_subj, dim3(grid1(K + 1)), dim3(256), 0, s, subj_ptr, row_ptr, K,
+                     n_rows, R, err, zbase, rbase);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_validate_rows, dim3(grid1(n_rows)), dim3(256), 0, s, row_ptr, col, val,
+                     n_rows, nnz, J, err);
+  return hipGetLastError();
+}
+
+hipError_t run_encode(const int64_t* subj_ptr, const int64_t* row_ptr, const int32_t* col,
+                      const float* val, int64_t K, int64_t nnz, const int32_t* rank,
+                      uint16_t* rstart, uint16_t* col16, float* val_out, double* nx2,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_encode_rows, dim3(grid1(K)), dim3(256), 0, s, subj_ptr, row_ptr, K, rstart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_encode_cols, dim3(grid1(nnz)), dim3(256), 0, s, col, val, nnz, rank, col16,
+                     val_out, nx2);
+  return hipGetLastError();
+}
+
+hipError_t run_col_hist(const int32_t* col, int64_t nnz, unsigned int* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_hist, dim3(grid1(nnz)), dim3(256), 0, s, col, nnz, hist);
+  return hipGetLastError();
+}
+
+hipError_t run_permute_rows(const float* src, float* dst, int64_t J, int R, int ld_src,
+                            int ld_dst, const int32_t* map, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute_rows, dim3(grid1(J * R)), dim3(256), 0, s, src, dst, J, R, ld_src,
+                     ld_dst, map);
+  return hipGetLastError();
+}
+
+hipError_t run_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid1(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t run_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid1(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t run_model_prep(int R, const double* VtV, const double* H, double* HtH, double* N3,
+                          double* N3p, const PolarParams& pp, hipStream_t s) {
+  P2_DISPATCH(R, hipLaunchKernelGGL(k_model_prep<RR>, dim3(1), dim3(64), 0, s, VtV, H, HtH, N3,
+                                    N3p, pp);
+              return hipGetLastError())
+}
+
+hipError_t run_iota(int32_t* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, dim3(grid1(n)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t run_fit(const double* fitacc, const double* nx2, double* fit_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fit, dim3(1), dim3(64), 0, s, fitacc, nx2, fit_out);
+  return hipGetLastError();
+}
+
+}  // namespace p2
