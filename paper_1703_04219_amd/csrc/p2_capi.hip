@@ -97,6 +97,8 @@ p2::PolarParams polar_params(const parafac2_opts* o, int R) {
   pp.tau_polar = (o && o->tau_polar > 0) ? o->tau_polar : 1e-10;
   pp.tau_pinv = (o && o->tau_pinv > 0) ? o->tau_pinv : R * 2.220446049250313e-16;
   pp.tol = 8.0 * 2.220446049250313e-16 * std::sqrt((double)NC);
+  pp.tau_c = 1e-12;
+  pp.tau_s = 1e-12;
   pp.max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 30;
   return pp;
 }
@@ -325,7 +327,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   // column frequencies -> relabelling (most frequent first, ties by id)
   uint32_t* hist = c->at<uint32_t>(plan.hist);
   INIT_TRY(hipMemsetAsync(hist, 0, sizeof(uint32_t) * X->J, s));
-  INIT_TRY(p2::run_col_hist(X->col, X->nnz, hist, s));
+  INIT_TRY(p2::run_col_hist(X->col, X->nnz, X->J, hist, s));
   std::vector<uint32_t> hh(X->J);
   INIT_TRY(hipMemcpyAsync(hh.data(), hist, sizeof(uint32_t) * X->J, hipMemcpyDeviceToHost, s));
   INIT_TRY(hipStreamSynchronize(s));

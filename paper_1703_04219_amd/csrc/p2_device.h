@@ -192,8 +192,8 @@ __device__ __forceinline__ void gram_accum(const double* A, const double* B, int
 // without rotations, so its result does not depend on other groups of the
 // wavefront.
 // ---------------------------------------------------------------------------
-template <int R>
-__device__ __forceinline__ void jacobi_onesided(double (&g)[R], double (&v)[R], int j, int gbase,
+template <int R, int N = R>
+__device__ __forceinline__ void jacobi_onesided(double (&g)[N], double (&v)[R], int j, int gbase,
                                                 uint64_t gmask, bool live, double tol,
                                                 int max_sweeps) {
   constexpr int NC = Geo<R>::NC;
@@ -211,9 +211,9 @@ __device__ __forceinline__ void jacobi_onesided(double (&g)[R], double (&v)[R], 
       const int src = gbase + (act ? partner : j);
       const bool lower = j < partner;
       double own2 = 0.0, gam = 0.0;
-      double pg[kKeepPartner ? R : 1];
+      double pg[kKeepPartner ? N : 1];
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
+      for (int i = 0; i < N; ++i) {
         const double p = __shfl(g[i], src);
         if constexpr (kKeepPartner) pg[i] = p;
         own2 = fma(g[i], g[i], own2);
@@ -238,16 +238,19 @@ __device__ __forceinline__ void jacobi_onesided(double (&g)[R], double (&v)[R], 
       const double a_own = lower ? sn : -sn;
       const double a_par = cs;
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
+      for (int i = 0; i < N; ++i) {
         double p;
         if constexpr (kKeepPartner)
           p = pg[i];
         else
           p = __shfl(g[i], src);
-        const double pv = __shfl(v[i], src);
         const double ng = fma(a_own, g[i], a_par * p);
-        const double nv = fma(a_own, v[i], a_par * pv);
         g[i] = act ? ng : g[i];
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const double pv = __shfl(v[i], src);
+        const double nv = fma(a_own, v[i], a_par * pv);
         v[i] = act ? nv : v[i];
       }
     }
@@ -363,6 +366,141 @@ __device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, con
     for (int i = 0; i < R; ++i) y[i] = 0.0;
   }
   wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Factored Procrustes step, used where the conditioning of B_k must not be
+// squared (projection of new subjects, where a weight passing near zero makes
+// B_k nearly singular).  C = A^T A is eigen-decomposed once (factor_c), giving
+// C = L L^T with L = E_C diag(s).  Each step then takes the one-sided Jacobi
+// SVD of the R x R factor T = L^T M^T (T^T T = G), T V = U Sigma, and
+//     Y V = V U^T L^T,     F = V U^T L^{-1}     (Q_k = A F^T),
+// so small singular values of B_k enter only through T, never through G.
+// ---------------------------------------------------------------------------
+
+// Eigen-decomposition of C (Cs, row-major, group LDS).  Writes row p of Ec =
+// eigenvector at position p, sv[p] = sqrt(lambda_p) and isv[p] = 1/sqrt(lambda_p)
+// (both 0 for lambda_p <= tau_c * lambda_max).
+template <int R>
+__device__ __forceinline__ void factor_c(const double* Cs, double* Ec, double* sv, double* isv,
+                                         double* dl, int c, int gbase, uint64_t gmask,
+                                         double tau_c, double tol, int max_sweeps) {
+  constexpr int NC = Geo<R>::NC;
+  double g[R], v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    g[i] = (c < R) ? Cs[i * R + c] : 0.0;
+    v[i] = (i == c) ? 1.0 : 0.0;
+  }
+  jacobi_onesided<R>(g, v, c, gbase, gmask, true, tol, max_sweeps);
+  double lam = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) lam = fma(v[i], g[i], lam);
+  dl[c] = lam;
+  wave_sync();
+  double lmax = 0.0;
+  for (int p = 0; p < NC; ++p) lmax = fmax(lmax, dl[p]);
+  wave_sync();
+  const bool keep = lam > tau_c * lmax && lam > 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) Ec[c * R + i] = v[i];
+  sv[c] = keep ? sqrt(lam) : 0.0;
+  isv[c] = keep ? 1.0 / sqrt(lam) : 0.0;
+  wave_sync();
+}
+
+// One factored Procrustes step.  On exit lane c (< R) holds (Y V)(:, c) in yv
+// and, if want_f, row c of F in fr.  S and S2 are group LDS scratch of
+// NC x R doubles each, dl of NC doubles.
+template <int R>
+__device__ __forceinline__ void polar_factored(const double* Ec, const double* sv,
+                                               const double* isv, const double* w,
+                                               const double* Hs, double* S, double* S2,
+                                               double* dl, int c, int gbase, uint64_t gmask,
+                                               double tau_s, double tol, int max_sweeps,
+                                               bool want_f, double (&yv)[R], double (&fr)[R]) {
+  constexpr int NC = Geo<R>::NC;
+  const bool real = c < R;
+  const int cc = real ? c : 0;
+  // column c of T:  T(p, c) = s_p  e_p . M(c, :),   M(c, l) = H(c, l) w(l)
+  double g[NC], v[R];
+  {
+    double mrow[R];
+#pragma unroll
+    for (int l = 0; l < R; ++l) mrow[l] = real ? Hs[cc * R + l] * w[l] : 0.0;
+#pragma unroll
+    for (int p = 0; p < NC; ++p) {
+      double t = 0.0;
+#pragma unroll
+      for (int l = 0; l < R; ++l) t = fma(Ec[p * R + l], mrow[l], t);
+      g[p] = sv[p] * t;
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = (i == c) ? 1.0 : 0.0;
+  }
+  jacobi_onesided<R, NC>(g, v, c, gbase, gmask, true, tol, max_sweeps);
+  double sig2 = 0.0;
+#pragma unroll
+  for (int p = 0; p < NC; ++p) sig2 = fma(g[p], g[p], sig2);
+  const double sig = sqrt(sig2);
+  dl[c] = sig;
+  wave_sync();
+  double smax = 0.0;
+  for (int p = 0; p < NC; ++p) smax = fmax(smax, dl[p]);
+  wave_sync();
+  const double inv_sig = (sig > tau_s * smax && sig > 0.0) ? 1.0 / sig : 0.0;
+  // y_c = L u_c = sum_p s_p u_c(p) e_p
+  {
+    double yl[R];
+#pragma unroll
+    for (int l = 0; l < R; ++l) yl[l] = 0.0;
+    for (int p = 0; p < NC; ++p) {
+      const double a = sv[p] * g[p] * inv_sig;
+#pragma unroll
+      for (int l = 0; l < R; ++l) yl[l] = fma(a, Ec[p * R + l], yl[l]);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      S[c * R + i] = v[i];
+      S2[c * R + i] = yl[i];
+    }
+  }
+  wave_sync();
+  // (Y V)(:, c) = sum_q v_q y_q(c)
+#pragma unroll
+  for (int i = 0; i < R; ++i) yv[i] = 0.0;
+  for (int q = 0; q < NC; ++q) {
+    const double yqc = S2[q * R + cc];
+#pragma unroll
+    for (int i = 0; i < R; ++i) yv[i] = fma(S[q * R + i], yqc, yv[i]);
+  }
+  if (!real) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) yv[i] = 0.0;
+  }
+  wave_sync();
+  if (want_f) {
+    // z_c = sum_p u_c(p) / s_p e_p;   F(c, :) = sum_q v_q(c) z_q
+    double zl[R];
+#pragma unroll
+    for (int l = 0; l < R; ++l) zl[l] = 0.0;
+    for (int p = 0; p < NC; ++p) {
+      const double a = isv[p] * g[p] * inv_sig;
+#pragma unroll
+      for (int l = 0; l < R; ++l) zl[l] = fma(a, Ec[p * R + l], zl[l]);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) S2[c * R + i] = zl[i];
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < R; ++i) fr[i] = 0.0;
+    for (int q = 0; q < NC; ++q) {
+      const double vqc = S[q * R + cc];
+#pragma unroll
+      for (int i = 0; i < R; ++i) fr[i] = fma(vqc, S2[q * R + i], fr[i]);
+    }
+    wave_sync();
+  }
 }
 
 }  // namespace p2

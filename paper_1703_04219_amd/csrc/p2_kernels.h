@@ -13,6 +13,8 @@ struct PolarParams {
   double tau_polar;  // relative eigenvalue cut in G^{-1/2}
   double tau_pinv;   // relative eigenvalue cut of the normal-equation pseudo-inverses
   double tol;        // Jacobi rotation threshold |g_p . g_q| > tol ||g_p|| ||g_q||
+  double tau_c;      // relative eigenvalue cut of C = A^T A in the factored polar
+  double tau_s;      // relative singular value cut of T in the factored polar
   int max_sweeps;
 };
 
@@ -55,7 +57,8 @@ hipError_t run_encode(const int64_t* subj_ptr, const int64_t* row_ptr, const int
                       const float* val, int64_t K, int64_t nnz, const int32_t* rank,
                       uint16_t* rstart, uint16_t* col16, float* val_out, double* nx2,
                       hipStream_t s);
-hipError_t run_col_hist(const int32_t* col, int64_t nnz, unsigned int* hist, hipStream_t s);
+hipError_t run_col_hist(const int32_t* col, int64_t nnz, int64_t J, unsigned int* hist,
+                        hipStream_t s);
 hipError_t run_permute_rows(const float* src, float* dst, int64_t J, int R, int ld_src,
                             int ld_dst, const int32_t* map, hipStream_t s);
 hipError_t run_fill_f64(double* p, int64_t n, double v, hipStream_t s);

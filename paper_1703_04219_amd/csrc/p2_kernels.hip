@@ -630,8 +630,25 @@ __global__ void __launch_bounds__(256) k_getq(XEnc X, int64_t k0, int64_t k1,
 
 // ---------------------------------------------------------------------------
 // projection of new subjects onto fixed (V, H): n_steps alternations of the
-// Procrustes step and the least-squares update of w (plain CSR input)
+// Procrustes step and the least-squares update of w (plain CSR input).  The
+// Procrustes step uses the factored form (polar_factored), with C = A^T A
+// eigen-decomposed once per subject.
 // ---------------------------------------------------------------------------
+template <int R>
+struct ProjLds {
+  static constexpr int NC = Geo<R>::NC;
+  static constexpr int oCs = 0;
+  static constexpr int oEc = oCs + R * R;
+  static constexpr int oS = oEc + NC * R;   // also the gather chunk
+  static constexpr int oS2 = oS + NC * R;
+  static constexpr int oSv = oS2 + NC * R;
+  static constexpr int oIsv = oSv + NC;
+  static constexpr int oW = oIsv + NC;
+  static constexpr int oM = oW + R;
+  static constexpr int oDl = oM + R;
+  static constexpr int kPerGroup = oDl + NC;
+};
+
 template <int R>
 __global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float* __restrict__ V,
                                                   const double* __restrict__ H,
@@ -643,20 +660,24 @@ __global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float*
                                                   double* __restrict__ lossout, PolarParams pp) {
   constexpr int NC = Geo<R>::NC;
   constexpr int GPW = Geo<R>::GPW;
-  constexpr int CH = PolarLds<R>::CH;
+  constexpr int CH = NC;
+  using PL = ProjLds<R>;
   const Lane L = lane_info<R>();
   const int wave = threadIdx.x / kWave;
   const int groups_per_block = (blockDim.x / kWave) * GPW;
   double* Hs = reinterpret_cast<double*>(p2_smem);
   double* N3s = Hs + R * R;
   double* N3ps = N3s + R * R;
-  double* gbuf = N3ps + R * R + (wave * GPW + (L.live ? L.grp : 0)) * PolarLds<R>::kPerGroup;
-  double* region = gbuf;
-  double* Cs = region;
-  double* S = region + R * R;
-  double* wv = gbuf + PolarLds<R>::kRegion;
-  double* mv = wv + R;
-  double* dl = mv + R;
+  double* gbuf = N3ps + R * R + (wave * GPW + (L.live ? L.grp : 0)) * PL::kPerGroup;
+  double* Cs = gbuf + PL::oCs;
+  double* Ec = gbuf + PL::oEc;
+  double* S = gbuf + PL::oS;
+  double* S2 = gbuf + PL::oS2;
+  double* sv = gbuf + PL::oSv;
+  double* isv = gbuf + PL::oIsv;
+  double* wv = gbuf + PL::oW;
+  double* mv = gbuf + PL::oM;
+  double* dl = gbuf + PL::oDl;
   load_shared_rxr<R>(Hs, H);
   load_shared_rxr<R>(N3s, N3);
   load_shared_rxr<R>(N3ps, N3p);
@@ -675,9 +696,9 @@ __global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float*
       for (int l = 0; l < R; ++l) crow[l] = 0.0;
       for (int i0 = 0; i0 < s.nrows; i0 += CH) {
         const int n = min(CH, s.nrows - i0);
-        gather_rows<R>(X, s, i0, n, V, region, c);
+        gather_rows<R>(X, s, i0, n, V, S, c);
         wave_sync();
-        gram_accum<R>(region, region, n, c, crow);
+        gram_accum<R>(S, S, n, c, crow);
         wave_sync();
       }
       if (real) {
@@ -694,14 +715,15 @@ __global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float*
       }
     }
     wave_sync();
-    double f[R], y[R], m3 = 0.0;
+    factor_c<R>(Cs, Ec, sv, isv, dl, c, L.gbase, L.gmask, pp.tau_c, pp.tol, pp.max_sweeps);
+    double yv[R], fr[R], m3 = 0.0;
 #pragma nounroll
     for (int step = 0; step < n_steps; ++step) {
-      polar_rxr<R>(Cs, wv, Hs, S, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
-                   pp.max_sweeps, f, y);
+      polar_factored<R>(Ec, sv, isv, wv, Hs, S, S2, dl, c, L.gbase, L.gmask, pp.tau_s, pp.tol,
+                        pp.max_sweeps, step + 1 == n_steps, yv, fr);
       m3 = 0.0;
 #pragma unroll
-      for (int i = 0; i < R; ++i) m3 = fma(Hs[i * R + cc], y[i], m3);
+      for (int i = 0; i < R; ++i) m3 = fma(Hs[i * R + cc], yv[i], m3);
       if (real) mv[c] = m3;
       wave_sync();
       double wn = 0.0;
@@ -726,28 +748,19 @@ __global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float*
       lossout[k] = loss;
     }
     wave_sync();
-    if (Qout) {
-      // Q = A F^T:  Q(i, c) = sum_p A(i, p) F(c, p); F(c, p) is element c of lane p's f
-      if (real) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) S[c * R + i] = f[i];
-      }
-      wave_sync();
-      float fr[R];
-#pragma unroll
-      for (int p = 0; p < R; ++p) fr[p] = (float)S[p * R + cc];
-      wave_sync();
-      float* Ab = reinterpret_cast<float*>(region);
+    if (Qout && n_steps > 0) {
+      // Q(i, c) = sum_p A(i, p) F(c, p)
+      float* Ab = reinterpret_cast<float*>(S);
       for (int i0 = 0; i0 < s.nrows; i0 += CH) {
         const int n = min(CH, s.nrows - i0);
         gather_rows<R>(X, s, i0, n, V, Ab, c);
         wave_sync();
         if (real) {
           for (int ii = 0; ii < n; ++ii) {
-            float q = 0.f;
+            double q = 0.0;
 #pragma unroll
-            for (int p = 0; p < R; ++p) q = fmaf(Ab[ii * R + p], fr[p], q);
-            Qout[(s.r0 + i0 + ii) * R + c] = q;
+            for (int p = 0; p < R; ++p) q = fma((double)Ab[ii * R + p], fr[p], q);
+            Qout[(s.r0 + i0 + ii) * R + c] = (float)q;
           }
         }
         wave_sync();
@@ -856,11 +869,31 @@ __global__ void k_encode_rows(const int64_t* __restrict__ subj_ptr,
   }
 }
 
-__global__ void k_col_hist(const int32_t* __restrict__ col, int64_t nnz,
+// Column histogram: block-private counts in LDS (J <= kHistLds), then one
+// global atomic per touched column per block.  Zipf-skewed columns make
+// direct global atomics on the hottest counters serialise.
+constexpr int kHistLds = 16384;
+
+__global__ void k_col_hist(const int32_t* __restrict__ col, int64_t nnz, int64_t J,
                            unsigned int* __restrict__ hist) {
+  __shared__ unsigned int sh[kHistLds];
+  const bool local = J <= kHistLds;
+  if (local) {
+    for (int i = threadIdx.x; i < J; i += blockDim.x) sh[i] = 0u;
+    __syncthreads();
+  }
   for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < nnz;
-       z += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&hist[col[z]], 1u);
+       z += (int64_t)gridDim.x * blockDim.x) {
+    if (local)
+      atomicAdd(&sh[col[z]], 1u);
+    else
+      atomicAdd(&hist[col[z]], 1u);
+  }
+  if (local) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < J; i += blockDim.x)
+      if (sh[i]) atomicAdd(&hist[i], sh[i]);
+  }
 }
 
 __global__ void k_encode_cols(const int32_t* __restrict__ col, const float* __restrict__ val,
@@ -1044,7 +1077,7 @@ hipError_t project_t(const XRaw& X, int64_t K, const float* V, const double* H, 
                      double* lossout, const PolarParams& pp, hipStream_t s) {
   constexpr int T = block_threads<R>();
   const int gpb = (T / kWave) * Geo<R>::GPW;
-  const size_t lds = sizeof(double) * (3 * R * R + (size_t)gpb * PolarLds<R>::kPerGroup);
+  const size_t lds = sizeof(double) * (3 * R * R + (size_t)gpb * ProjLds<R>::kPerGroup);
   hipError_t e = allow_lds(k_project<R>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_project<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V, H, N3, N3p,
@@ -1174,8 +1207,11 @@ hipError_t run_encode(const int64_t* subj_ptr, const int64_t* row_ptr, const int
   return hipGetLastError();
 }
 
-hipError_t run_col_hist(const int32_t* col, int64_t nnz, unsigned int* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_hist, dim3(grid1(nnz)), dim3(256), 0, s, col, nnz, hist);
+hipError_t run_col_hist(const int32_t* col, int64_t nnz, int64_t J, unsigned int* hist,
+                        hipStream_t s) {
+  int blocks = grid1(nnz);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_col_hist, dim3(blocks), dim3(256), 0, s, col, nnz, J, hist);
   return hipGetLastError();
 }
 

@@ -158,6 +158,39 @@ def test_projection_matches_oracle():
     assert np.max(np.abs(loss - np.array(ls)) / nx) <= 1e-5
 
 
+def test_projection_alone_equals_in_the_mix():
+    # each subject's result depends only on its own slice: projecting a request
+    # alone or inside a batch gives the same bits
+    V, H = gen_serving_model()
+    _, Xr = gen_serving_requests(16)
+    model = B.Model(V, H)
+    Qb, wb, lb = model.project(B.DeviceSlices.from_slices(Xr), n_steps=10)
+    torch.cuda.synchronize()
+    for k in (0, 5, 15):
+        Xk = take_subjects(Xr, k, k + 1)
+        Q1, w1, l1 = model.project(B.DeviceSlices.from_slices(Xk), n_steps=10)
+        torch.cuda.synchronize()
+        r0, r1 = int(Xr.subj_ptr[k]), int(Xr.subj_ptr[k + 1])
+        assert torch.equal(w1[0], wb[k])
+        assert torch.equal(l1[0], lb[k])
+        assert torch.equal(Q1, Qb[r0:r1])
+
+
+def test_projection_q_is_orthonormal():
+    V, H = gen_serving_model()
+    _, Xr = gen_serving_requests(8)
+    model = B.Model(V, H)
+    Q, w, _ = model.project(B.DeviceSlices.from_slices(Xr), n_steps=10)
+    Q = Q.cpu().numpy().astype(np.float64)
+    Xs = _xs(Xr)
+    for k in range(Xr.K):
+        r0, r1 = Xr.subj_ptr[k], Xr.subj_ptr[k + 1]
+        Qk = Q[r0:r1]
+        assert np.abs(Qk.T @ Qk - np.eye(Qk.shape[1])).max() <= 1e-5
+        Qo, _, _ = O.project(Xs[k], V.astype(np.float64), H, n_steps=10)
+        assert rel(Qk, Qo) <= 1e-4
+
+
 def test_invalid_input_is_rejected():
     X, R = gen_config(1)
     bad = X.col.copy()
