@@ -43,7 +43,8 @@ constexpr int kFitRing = 1024;
 
 // Offsets of every piece of the context workspace.
 struct Plan {
-  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, V[2], F, M2, M3, small, err, total;
+  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, V[2], F, M2, M2part, M3, small, err,
+      total;
   // small block (doubles)
   size_t oM1, oWtW, oVtV, oVtVraw, oHtH, oN2p, oN3, oN3p, oInv, oFitAcc, oNx2, oFits, nsmall;
 };
@@ -69,6 +70,7 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R) {
   p.V[1] = take(sizeof(float) * J * LDV);
   p.F = take(sizeof(float) * (size_t)K * R * R);
   p.M2 = take(sizeof(float) * J * LDV);
+  p.M2part = take(p2::mode2_part_bytes(R, K, (int)std::min<int64_t>(p2::mode2_max_hot(R), J)));
   p.M3 = take(sizeof(float) * (size_t)K * R);
   const size_t RR = (size_t)R * R;
   size_t s = 0;
@@ -413,7 +415,8 @@ static int iterate_impl(parafac2_ctx* c, int32_t n_iters, double* fit_host) {
           HIP_TRY(p2::run_solve_h(R, M1, WtW, VtV, c->H, HtH, N2p, c->pp, s)));
     // mode 2 -> V
     HIP_TRY(p2::run_fill_f32(M2, c->J * c->LDV, 0.f, s));
-    PHASE(P2_PHASE_MODE2, HIP_TRY(p2::run_mode2(R, c->X, c->K, Vc, c->W, c->H, F, M2, c->hot, s)));
+    PHASE(P2_PHASE_MODE2, HIP_TRY(p2::run_mode2(R, c->X, c->K, Vc, c->W, c->H, F, M2,
+                                                 c->at<float>(P.M2part), c->hot, s)));
     PHASE(P2_PHASE_VUPDATE, HIP_TRY(p2::run_vupdate(R, M2, N2p, c->J, Vn, s));
           HIP_TRY(p2::run_fill_f64(VtVraw, RR, 0.0, s));
           HIP_TRY(p2::run_gram_tall(R, Vn, c->J, c->LDV, VtVraw, s));

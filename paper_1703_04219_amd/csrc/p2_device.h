@@ -182,79 +182,146 @@ __device__ __forceinline__ void gram_accum(const double* A, const double* B, int
 }
 
 // ---------------------------------------------------------------------------
-// One-sided (Hestenes) Jacobi on the symmetric PSD matrix G, column per lane.
-// On entry lane j of the group holds g = G(:, j) and v = e_j (zero columns on
-// the padding lane).  Pairs of positions rotate and then swap ("caterpillar"
-// odd-even ordering: positions (2t, 2t+1) on even steps, (2t+1, 2t+2) on odd
-// steps; NC steps make every pair meet once).  At convergence G v_j = g_j with
-// orthonormal v_j, i.e. the v_j are eigenvectors of G and v_j^T g_j are the
-// eigenvalues.  A group stops rotating (and swapping) after a full sweep
-// without rotations, so its result does not depend on other groups of the
-// wavefront.
+// Cross-lane moves with DPP (no LDS traffic).  quad_perm [1,0,3,2] swaps
+// lanes 2t and 2t+1; wave_shl:1 reads lane i+1, wave_shr:1 reads lane i-1.
 // ---------------------------------------------------------------------------
-template <int R, int N = R>
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __double2loint(x);
+  const int hi = __double2hiint(x);
+  // lanes without a valid source read 0; only in-group partners are used
+  const int lo2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  const int hi2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi2, lo2);
+}
+constexpr int kDppSwapPairs = 0xB1;  // quad_perm:[1,0,3,2]
+constexpr int kDppFromNext = 0x130;  // wave_shl:1
+constexpr int kDppFromPrev = 0x138;  // wave_shr:1
+
+// Value of the Jacobi partner.  Even steps pair lanes (2t, 2t+1); odd steps
+// pair (2t+1, 2t+2): an odd lane reads lane+1, an even lane lane-1.  Groups
+// start at even lanes, so lane parity equals position parity.
+template <bool ODD>
+__device__ __forceinline__ double partner_of(double x, bool lane_odd) {
+  if constexpr (!ODD) {
+    return dpp_f64<kDppSwapPairs>(x);
+  } else {
+    const double a = dpp_f64<kDppFromNext>(x);
+    const double b = dpp_f64<kDppFromPrev>(x);
+    return lane_odd ? a : b;
+  }
+}
+
+// 1/sqrt(x) and 1/x in FP64 from the hardware approximations plus two
+// Newton steps each (rotation parameters need c^2 + s^2 = 1 to working
+// precision, not correct rounding).
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi on the columns of a matrix, one column per lane.
+// On entry lane j of the group holds g = column j (length N) and v = e_j
+// (zero columns on the padding lane).  Pairs of positions rotate and then
+// swap ("caterpillar" odd-even ordering: positions (2t, 2t+1) on even steps,
+// (2t+1, 2t+2) on odd steps; NC steps make every pair meet once).  At
+// convergence the columns g_j = (input) v_j are mutually orthogonal and the
+// v_j orthonormal: for a symmetric PSD input the v_j are its eigenvectors.
+// For a symmetric PSD input the rotations need not be accumulated (ACCUM =
+// false): G^2 = sum_j g_j g_j^T with orthogonal g_j, so g_j / ||g_j|| is an
+// eigenvector of G with eigenvalue ||g_j||.
+// A group stops (no rotation, no swap) after a sweep whose rotations were all
+// below 1e-9 in relative size -- Jacobi converges quadratically, so the
+// columns are then orthogonal to working precision -- which keeps its result
+// independent of the other groups of the wavefront.
+// ---------------------------------------------------------------------------
+template <int R, int N, bool ODD, bool ACCUM>
+__device__ __forceinline__ void jacobi_step(double (&g)[N], double (&v)[R], int j, bool lane_odd,
+                                            bool done, double tol2, bool& rot, bool& big) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr bool kKeepPartner = N <= 20;
+  const int partner = ODD ? (lane_odd ? j + 1 : j - 1) : (j ^ 1);
+  const bool act = !done && (!ODD || (j != 0 && j != NC - 1));
+  const bool lower = j < partner;
+  double own2 = 0.0, gam = 0.0;
+  double pg[kKeepPartner ? N : 1];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double p = partner_of<ODD>(g[i], lane_odd);
+    if constexpr (kKeepPartner) pg[i] = p;
+    own2 = fma(g[i], g[i], own2);
+    gam = fma(g[i], p, gam);
+  }
+  const double par2 = partner_of<ODD>(own2, lane_odd);
+  const double alpha = lower ? own2 : par2;
+  const double beta = lower ? par2 : own2;
+  // rotation (c, s) zeroing the pair's inner product, t = s / c
+  double cs = 1.0, sn = 0.0;
+  const double g2 = gam * gam;
+  const double ab = alpha * beta;
+  if (act && g2 > tol2 * ab) {
+    const double d = beta - alpha;
+    const double e = 2.0 * gam;
+    const double h2 = fma(d, d, e * e);
+    const double h = h2 * rsq_nr(h2);
+    const double t = copysign(1.0, d) * e * rcp_nr(fabs(d) + h);
+    cs = rsq_nr(fma(t, t, 1.0));
+    sn = cs * t;
+    rot = true;
+    if (g2 > 1e-18 * ab) big = true;
+  }
+  // rotate and swap: the lower position receives s x + c y, the upper c x - s y;
+  // a lane that does not take part keeps its column (coefficients 1, 0)
+  const double a_own = act ? (lower ? sn : -sn) : 1.0;
+  const double a_par = act ? cs : 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double p;
+    if constexpr (kKeepPartner)
+      p = pg[i];
+    else
+      p = partner_of<ODD>(g[i], lane_odd);
+    g[i] = fma(a_own, g[i], a_par * p);
+  }
+  if constexpr (ACCUM) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const double pv = partner_of<ODD>(v[i], lane_odd);
+      v[i] = fma(a_own, v[i], a_par * pv);
+    }
+  }
+}
+
+template <int R, int N = R, bool ACCUM = true>
 __device__ __forceinline__ void jacobi_onesided(double (&g)[N], double (&v)[R], int j, int gbase,
                                                 uint64_t gmask, bool live, double tol,
                                                 int max_sweeps) {
   constexpr int NC = Geo<R>::NC;
-  constexpr bool kKeepPartner = R <= 20;
+  static_assert(NC % 2 == 0, "groups have an even number of lanes");
+  const bool lane_odd = (j & 1) != 0;
+  const double tol2 = tol * tol;
   bool done = !live;
 #pragma nounroll
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (__ballot(!done) == 0ull) break;
-    bool rot = false;
+    bool rot = false, big = false;
 #pragma nounroll
-    for (int step = 0; step < NC; ++step) {
-      const bool odd = (step & 1) != 0;
-      const int partner = odd ? ((j & 1) ? j + 1 : j - 1) : (j ^ 1);
-      const bool act = !done && (!odd || (j != 0 && j != NC - 1));
-      const int src = gbase + (act ? partner : j);
-      const bool lower = j < partner;
-      double own2 = 0.0, gam = 0.0;
-      double pg[kKeepPartner ? N : 1];
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const double p = __shfl(g[i], src);
-        if constexpr (kKeepPartner) pg[i] = p;
-        own2 = fma(g[i], g[i], own2);
-        gam = fma(g[i], p, gam);
-      }
-      const double par2 = __shfl(own2, src);
-      const double alpha = lower ? own2 : par2;
-      const double beta = lower ? par2 : own2;
-      double cs = 1.0, sn = 0.0;
-      if (act && fabs(gam) > tol * sqrt(alpha * beta)) {
-        const double zeta = (beta - alpha) / (2.0 * gam);
-        double t;
-        if (fabs(zeta) > 1e150)
-          t = 0.5 / zeta;
-        else
-          t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        cs = 1.0 / sqrt(1.0 + t * t);
-        sn = cs * t;
-        rot = true;
-      }
-      // lower position receives y' = s x + c y, upper receives x' = c x - s y
-      const double a_own = lower ? sn : -sn;
-      const double a_par = cs;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        double p;
-        if constexpr (kKeepPartner)
-          p = pg[i];
-        else
-          p = __shfl(g[i], src);
-        const double ng = fma(a_own, g[i], a_par * p);
-        g[i] = act ? ng : g[i];
-      }
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const double pv = __shfl(v[i], src);
-        const double nv = fma(a_own, v[i], a_par * pv);
-        v[i] = act ? nv : v[i];
-      }
+    for (int step = 0; step < NC; step += 2) {
+      jacobi_step<R, N, false, ACCUM>(g, v, j, lane_odd, done, tol2, rot, big);
+      jacobi_step<R, N, true, ACCUM>(g, v, j, lane_odd, done, tol2, rot, big);
     }
-    if ((__ballot(rot) & gmask) == 0ull) done = true;
+    (void)rot;
+    if ((__ballot(big) & gmask) == 0ull) done = true;
   }
 }
 
@@ -310,19 +377,23 @@ __device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, con
     for (int i = 0; i < R; ++i) v[i] = (i == c) ? 1.0 : 0.0;
   }
   wave_sync();
-  jacobi_onesided<R>(g, v, c, gbase, gmask, live, tol, max_sweeps);
-  // eigenvalue at this position and the group's largest one
-  double lam = 0.0;
+  jacobi_onesided<R, R, false>(g, v, c, gbase, gmask, live, tol, max_sweeps);
+  // eigenvalue ||g|| and eigenvector g / ||g|| at this position, and the
+  // group's largest eigenvalue
+  double lam2 = 0.0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) lam = fma(v[i], g[i], lam);
+  for (int i = 0; i < R; ++i) lam2 = fma(g[i], g[i], lam2);
+  const double lam = sqrt(lam2);
   dl[c] = lam;
   wave_sync();
   double lmax = 0.0;
   for (int p = 0; p < NC; ++p) lmax = fmax(lmax, dl[p]);
   wave_sync();
-  const double d = (lam > tau * lmax && lam > 0.0) ? 1.0 / sqrt(lam) : 0.0;
+  const bool keep = lam > tau * lmax && lam > 0.0;
+  const double d = keep ? 1.0 / sqrt(lam) : 0.0;
+  const double inv_lam = keep ? 1.0 / lam : 0.0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) S[c * R + i] = v[i];
+  for (int i = 0; i < R; ++i) S[c * R + i] = g[i] * inv_lam;
   dl[c] = d;
   wave_sync();
   // F(:, c) = sum_p d_p v_p (v_p . M(:, c)),   M(:, c) = H(:, c) w(c)

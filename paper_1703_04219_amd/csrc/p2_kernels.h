@@ -32,7 +32,10 @@ hipError_t run_gamma(int R, const XEnc& X, int64_t K, const float* V0, const flo
                      double* M1next, double* fitacc, int do_next, const PolarParams& pp,
                      hipStream_t s);
 hipError_t run_mode2(int R, const XEnc& X, int64_t K, const float* V, const float* W,
-                     const double* H, const float* F, float* M2, int hot, hipStream_t s);
+                     const double* H, const float* F, float* M2, float* part, int hot,
+                     hipStream_t s);
+// Bytes of the per-block partial sums that run_mode2 writes.
+size_t mode2_part_bytes(int R, int64_t K, int hot);
 hipError_t run_gram_tall(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s);
 hipError_t run_solve_h(int R, const double* M1, const double* WtW, const double* VtV, double* H,
                        double* HtH, double* N2p, const PolarParams& pp, hipStream_t s);

@@ -303,24 +303,34 @@ __global__ void __launch_bounds__(256) k_gamma(XEnc X, int64_t K, const float* _
 }
 
 // ---------------------------------------------------------------------------
-// k_mode2: M2 += X_k^T (A_k E_k),  E_k = F_k^T H S_k  (equation (mttkrp2_3))
+// k_mode2: M2 += X_k^T (A_k E_k),  E_k = F_k^T H diag(w_k)  (equation
+// (mttkrp2_3): for every nonzero column j of X_k, row j of Y_k^T H diag(w_k)).
+// One lane per row: it gathers A(i, :) into registers, forms D(i, :) =
+// A(i, :) E_k with E_k staged in the group's LDS, and adds x_ij D(i, :) into
+// M2(j, :) -- in the block's LDS copy for the hot columns (ids < hot, the most
+// frequent after relabelling), with global atomics for the rest.  Each block
+// writes its hot partial sums to part[blockIdx] without atomics;
+// k_mode2_reduce adds them up.
 // ---------------------------------------------------------------------------
+constexpr int kMode2Threads = 1024;
+
 template <int R>
-__global__ void __launch_bounds__(256) k_mode2(XEnc X, int64_t K, const float* __restrict__ V,
-                                                const float* __restrict__ W,
-                                                const double* __restrict__ H,
-                                                const float* __restrict__ F,
-                                                float* __restrict__ M2, int hot) {
+__global__ void __launch_bounds__(kMode2Threads) k_mode2(XEnc X, int64_t K,
+                                                          const float* __restrict__ V,
+                                                          const float* __restrict__ W,
+                                                          const double* __restrict__ H,
+                                                          const float* __restrict__ F,
+                                                          float* __restrict__ M2,
+                                                          float* __restrict__ part, int hot) {
   constexpr int NC = Geo<R>::NC;
   constexpr int GPW = Geo<R>::GPW;
   constexpr int LDV = Geo<R>::LDV;
-  constexpr int CH = NC;
   const Lane L = lane_info<R>();
   const int wave = threadIdx.x / kWave;
   const int groups_per_block = (blockDim.x / kWave) * GPW;
-  float* shM2 = reinterpret_cast<float*>(p2_smem);  // hot x LDV
-  float* gbuf = shM2 + (size_t)hot * LDV + (wave * GPW + (L.live ? L.grp : 0)) * (CH * R);
-  for (int i = threadIdx.x; i < hot * LDV; i += blockDim.x) shM2[i] = 0.f;
+  float* shM2 = reinterpret_cast<float*>(p2_smem);  // hot x R
+  float* Es = shM2 + (size_t)hot * R + (wave * GPW + (L.live ? L.grp : 0)) * (R * R);
+  for (int i = threadIdx.x; i < hot * R; i += blockDim.x) shM2[i] = 0.f;
   __syncthreads();
 
   const int c = L.j;
@@ -334,9 +344,8 @@ __global__ void __launch_bounds__(256) k_mode2(XEnc X, int64_t K, const float* _
     const int64_t stride = (int64_t)gridDim.x * groups_per_block;
     for (int64_t k = gid; k < K; k += stride) {
       const Subj s = X.subj(k);
-      // E(:, c) = w(c) F^T H(:, c)
-      float e[R];
       {
+        // E(:, c) = w(c) F^T H(:, c), stored row-major E(p, c) = Es[p * R + c]
         const float* Fk = F + (size_t)k * R * R;
         const float wc = W[k * R + cc];
 #pragma unroll
@@ -344,39 +353,70 @@ __global__ void __launch_bounds__(256) k_mode2(XEnc X, int64_t K, const float* _
           float t = 0.f;
 #pragma unroll
           for (int i = 0; i < R; ++i) t = fmaf(Fk[p * R + i], hc[i], t);
-          e[p] = t * wc;
+          if (real) Es[p * R + c] = t * wc;
         }
       }
-      for (int i0 = 0; i0 < s.nrows; i0 += CH) {
-        const int n = min(CH, s.nrows - i0);
-        gather_rows<R>(X, s, i0, n, V, gbuf, c);
-        wave_sync();
+      wave_sync();
+#pragma nounroll
+      for (int ii = c; ii < s.nrows; ii += NC) {
         int zs, ze;
-        X.row(s, i0, zs, ze);
-        for (int ii = 0; ii < n; ++ii) {
-          float d = 0.f;
+        X.row(s, ii, zs, ze);
+        float a[LDV];
 #pragma unroll
-          for (int p = 0; p < R; ++p) d = fmaf(gbuf[ii * R + p], e[p], d);
-          if (ii > 0) X.row(s, i0 + ii, zs, ze);
-          for (int z = zs; z < ze; ++z) {
-            const int j = X.colat(s, z);
-            const float v = X.valat(s, z) * d;
-            if (real) {
-              if (j < hot)
-                atomicAdd(&shM2[j * LDV + c], v);
-              else
-                atomicAdd(&M2[(size_t)j * LDV + c], v);
-            }
+        for (int q = 0; q < LDV; ++q) a[q] = 0.f;
+        for (int z = zs; z < ze; ++z) {
+          const float x = X.valat(s, z);
+          const float4* vr = reinterpret_cast<const float4*>(V + (size_t)X.colat(s, z) * LDV);
+#pragma unroll
+          for (int q = 0; q < LDV / 4; ++q) {
+            const float4 t = vr[q];
+            a[4 * q + 0] = fmaf(x, t.x, a[4 * q + 0]);
+            a[4 * q + 1] = fmaf(x, t.y, a[4 * q + 1]);
+            a[4 * q + 2] = fmaf(x, t.z, a[4 * q + 2]);
+            a[4 * q + 3] = fmaf(x, t.w, a[4 * q + 3]);
           }
         }
-        wave_sync();
+        float d[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) d[q] = 0.f;
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+#pragma unroll
+          for (int q = 0; q < R; ++q) d[q] = fmaf(a[p], Es[p * R + q], d[q]);
+        }
+        for (int z = zs; z < ze; ++z) {
+          const int j = X.colat(s, z);
+          const float x = X.valat(s, z);
+          if (j < hot) {
+            float* dst = shM2 + j * R;
+#pragma unroll
+            for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
+          } else {
+            float* dst = M2 + (size_t)j * LDV;
+#pragma unroll
+            for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
+          }
+        }
       }
+      wave_sync();
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < hot * LDV; i += blockDim.x) {
-    const float v = shM2[i];
-    if (v != 0.f) atomicAdd(&M2[i], v);
+  float* mine = part + (size_t)blockIdx.x * hot * R;
+  for (int i = threadIdx.x; i < hot * R; i += blockDim.x) mine[i] = shM2[i];
+}
+
+// M2(j, :) += sum over blocks of part[b](j, :) for the hot columns
+template <int R>
+__global__ void __launch_bounds__(256) k_mode2_reduce(const float* __restrict__ part, int nblocks,
+                                                       int hot, float* __restrict__ M2) {
+  constexpr int LDV = Geo<R>::LDV;
+  const int n = hot * R;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    float acc = 0.f;
+    for (int b = 0; b < nblocks; ++b) acc += part[(size_t)b * n + t];
+    const int j = t / R, q = t - j * R;
+    M2[(size_t)j * LDV + q] += acc;
   }
 }
 
@@ -429,19 +469,21 @@ __device__ void pinv_cols(const double (&ncol)[R], int c, double* S, double* dl,
     v[i] = (i == c) ? 1.0 : 0.0;
   }
   const uint64_t gmask = (NC == 64) ? ~0ull : ((1ull << NC) - 1ull);
-  jacobi_onesided<R>(g, v, c, 0, gmask, c < NC, tol, max_sweeps);
-  double lam = 0.0;
+  jacobi_onesided<R, R, false>(g, v, c, 0, gmask, c < NC, tol, max_sweeps);
+  double lam2 = 0.0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) lam = fma(v[i], g[i], lam);
+  for (int i = 0; i < R; ++i) lam2 = fma(g[i], g[i], lam2);
+  const double lam = sqrt(lam2);
   if (c < NC) dl[c] = lam;
   __syncthreads();
   double lmax = 0.0;
   for (int p = 0; p < NC; ++p) lmax = fmax(lmax, dl[p]);
   __syncthreads();
-  const double inv = (lam > tau * lmax && lam > 0.0) ? 1.0 / lam : 0.0;
+  const bool keep = lam > tau * lmax && lam > 0.0;
+  const double inv = keep ? 1.0 / lam : 0.0;
   if (c < NC) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) S[c * R + i] = v[i];
+    for (int i = 0; i < R; ++i) S[c * R + i] = g[i] * inv;
     dl[c] = inv;
   }
   __syncthreads();
@@ -1026,27 +1068,35 @@ hipError_t gamma_t(const XEnc& X, int64_t K, const float* V0, const float* V1, f
 
 template <int R>
 int mode2_group_floats() {
-  constexpr int T = block_threads<R>();
-  return (T / kWave) * Geo<R>::GPW * Geo<R>::NC * R;
+  return (kMode2Threads / kWave) * Geo<R>::GPW * R * R;
 }
 
 template <int R>
 int max_hot_t() {
-  // leave room for two resident blocks per CU
-  const int budget = kLdsPerCu / 2 - mode2_group_floats<R>() * 4 - 1024;
-  return budget / (Geo<R>::LDV * 4);
+  // one 1024-thread block per CU: the hot partial sums take what the per-group
+  // E_k buffers leave of the LDS
+  const int budget = kLdsPerCu - mode2_group_floats<R>() * 4 - 2048;
+  return budget / (R * 4);
 }
+
+int mode2_blocks(int64_t K, int gpb) { return grid_for(K, gpb) < 256 ? grid_for(K, gpb) : 256; }
 
 template <int R>
 hipError_t mode2_t(const XEnc& X, int64_t K, const float* V, const float* W, const double* H,
-                   const float* F, float* M2, int hot, hipStream_t s) {
-  constexpr int T = block_threads<R>();
+                   const float* F, float* M2, float* part, int hot, hipStream_t s) {
+  constexpr int T = kMode2Threads;
   const int gpb = (T / kWave) * Geo<R>::GPW;
-  const size_t lds = sizeof(float) * ((size_t)hot * Geo<R>::LDV + mode2_group_floats<R>());
+  const size_t lds = sizeof(float) * ((size_t)hot * R + mode2_group_floats<R>());
   hipError_t e = allow_lds(k_mode2<R>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mode2<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V, W, H, F, M2,
-                     hot);
+  const int nb = mode2_blocks(K, gpb);
+  hipLaunchKernelGGL(k_mode2<R>, dim3(nb), dim3(T), lds, s, X, K, V, W, H, F, M2, part, hot);
+  e = hipGetLastError();
+  if (e != hipSuccess || hot == 0) return e;
+  const int n = hot * R;
+  int rb = (n + 255) / 256;
+  if (rb > 1024) rb = 1024;
+  hipLaunchKernelGGL(k_mode2_reduce<R>, dim3(rb), dim3(256), 0, s, part, nb, hot, M2);
   return hipGetLastError();
 }
 
@@ -1134,8 +1184,25 @@ hipError_t run_gamma(int R, const XEnc& X, int64_t K, const float* V0, const flo
 }
 
 hipError_t run_mode2(int R, const XEnc& X, int64_t K, const float* V, const float* W,
-                     const double* H, const float* F, float* M2, int hot, hipStream_t s) {
-  P2_DISPATCH(R, return mode2_t<RR>(X, K, V, W, H, F, M2, hot, s))
+                     const double* H, const float* F, float* M2, float* part, int hot,
+                     hipStream_t s) {
+  P2_DISPATCH(R, return mode2_t<RR>(X, K, V, W, H, F, M2, part, hot, s))
+}
+
+size_t mode2_part_bytes(int R, int64_t K, int hot) {
+  int gpw = 0;
+  switch (R) {
+#define P2_CASE(r) \
+  case r:          \
+    gpw = Geo<r>::GPW; \
+    break;
+    P2_RANKS(P2_CASE)
+#undef P2_CASE
+    default:
+      return 0;
+  }
+  const int gpb = (kMode2Threads / kWave) * gpw;
+  return sizeof(float) * (size_t)mode2_blocks(K, gpb) * (size_t)hot * R;
 }
 
 hipError_t run_gram_tall(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s) {
