@@ -38,7 +38,22 @@ def parse():
                    help="subjects in the oracle's timed sample (0 = skip)")
     p.add_argument("--profile-only", action="store_true",
                    help="skip the CPU baseline (for profiler runs)")
+    p.add_argument("--copy-bytes", type=int, default=0,
+                   help="only run a plain device-to-device copy of this many bytes (calibrates "
+                        "the profiler's FETCH_SIZE / WRITE_SIZE counters) and exit")
     return p.parse_args()
+
+
+def copy_calibration(nbytes: int):
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "launches": 3}), flush=True)
 
 
 def stream_bytes(X, R: int) -> dict:
@@ -70,6 +85,9 @@ def cpu_baseline(cfg: int, n_subjects: int):
 
 def main():
     a = parse()
+    if a.copy_bytes:
+        copy_calibration(a.copy_bytes)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
               "subject-sharded design is described but not built.", file=sys.stderr)
@@ -79,12 +97,13 @@ def main():
     from datagen import CONFIGS, gen_config, gen_init
     from paper_1703_04219_amd import binding as B
 
-    torch.cuda.set_device(0)
+    # draw the input before the GPU runtime starts (the generator forks workers)
     t0 = time.perf_counter()
     X, R = gen_config(a.config, k_limit=a.k_limit)
     H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, a.config, 1])
     print(f"[bench] generated K={X.K} J={X.J} R={R} rows={X.n_rows} nnz={X.nnz} "
           f"in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
     dX = B.DeviceSlices.from_slices(X)
     ctx = B.Context(dX, R, H0, V0, W0)
     del dX  # the context re-encoded the input into its workspace

@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Callable, Optional
 
 import numpy as np
@@ -107,6 +108,34 @@ def _distinct_sorted_rows(rng, row_id: np.ndarray, J: int, draw) -> np.ndarray:
     raise RuntimeError("could not draw distinct columns")
 
 
+def _gpu_runtime_started() -> bool:
+    import sys
+    torch = sys.modules.get("torch")
+    try:
+        return bool(torch is not None and torch.cuda.is_initialized())
+    except Exception:
+        return True
+
+
+def _gen_chunk(args):
+    """One chunk of subjects (runs in a worker process for large inputs)."""
+    (child, nk, take, J, ik_range, nnz_row, col_dist, zipf_s, perm_seed) = args
+    draw = make_col_sampler(J, col_dist, zipf_s, perm_seed=perm_seed)
+    rng = np.random.default_rng(child)
+    Ik = rng.integers(ik_range[0], ik_range[1] + 1, size=nk, dtype=np.int64)
+    nr = int(Ik.sum())
+    rl = np.asarray(nnz_row(rng, nr), dtype=np.int64)
+    np.clip(rl, 1, J, out=rl)
+    row_id = np.repeat(np.arange(nr, dtype=np.int64), rl)
+    cols = _distinct_sorted_rows(rng, row_id, J, draw)
+    vals = (1.0 - rng.random(cols.shape[0])).astype(np.float32)
+    if take < nk:
+        nr_t = int(Ik[:take].sum())
+        nz_t = int(rl[:nr_t].sum())
+        Ik, rl, cols, vals = Ik[:take], rl[:nr_t], cols[:nz_t], vals[:nz_t]
+    return Ik, rl, cols, vals
+
+
 def gen_slices(
     K: int,
     J: int,
@@ -117,53 +146,61 @@ def gen_slices(
     zipf_s: float = 1.1,
     chunk: int = CHUNK,
     k_limit: Optional[int] = None,
+    workers: Optional[int] = None,
 ) -> Slices:
     """Generate K slices chunk by chunk.  seed is a sequence of ints; chunk c uses
-    child c of SeedSequence(seed); the column permutation uses seed + [2]."""
+    child c of SeedSequence(seed); the column permutation uses seed + [2].
+    Chunks are independent, so large inputs are drawn by a process pool; the
+    result does not depend on the number of workers."""
     seed = list(seed)
     n_chunks = (K + chunk - 1) // chunk
     children = np.random.SeedSequence(seed).spawn(n_chunks)
-    draw = make_col_sampler(J, col_dist, zipf_s, perm_seed=np.random.SeedSequence(seed + [2]))
+    perm_seed = np.random.SeedSequence(seed + [2])
     k_stop = K if k_limit is None else min(K, k_limit)
-    I_parts, rl_parts, col_parts, val_parts = [], [], [], []
+    jobs = []
     for c in range((k_stop + chunk - 1) // chunk):
-        rng = np.random.default_rng(children[c])
         nk = min(chunk, K - c * chunk)
-        Ik = rng.integers(ik_range[0], ik_range[1] + 1, size=nk, dtype=np.int64)
-        nr = int(Ik.sum())
-        rl = np.asarray(nnz_row(rng, nr), dtype=np.int64)
-        np.clip(rl, 1, J, out=rl)
-        row_id = np.repeat(np.arange(nr, dtype=np.int64), rl)
-        cols = _distinct_sorted_rows(rng, row_id, J, draw)
-        vals = (1.0 - rng.random(cols.shape[0])).astype(np.float32)
         take = min(nk, k_stop - c * chunk)
-        if take < nk:
-            nr_t = int(Ik[:take].sum())
-            nz_t = int(rl[:nr_t].sum())
-            Ik, rl, cols, vals = Ik[:take], rl[:nr_t], cols[:nz_t], vals[:nz_t]
-        I_parts.append(Ik)
-        rl_parts.append(rl)
-        col_parts.append(cols)
-        val_parts.append(vals)
-    Ik = np.concatenate(I_parts)
-    rl = np.concatenate(rl_parts)
+        jobs.append((children[c], nk, take, J, ik_range, nnz_row, col_dist, zipf_s, perm_seed))
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if len(jobs) >= 8 else 1
+        if _gpu_runtime_started():
+            workers = 1  # never fork a process that holds a GPU context
+    if workers > 1:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+            parts = list(ex.map(_gen_chunk, jobs, chunksize=1))
+    else:
+        parts = [_gen_chunk(j) for j in jobs]
+    Ik = np.concatenate([q[0] for q in parts])
+    rl = np.concatenate([q[1] for q in parts])
     subj_ptr = np.zeros(Ik.shape[0] + 1, dtype=np.int64)
     np.cumsum(Ik, out=subj_ptr[1:])
     row_ptr = np.zeros(rl.shape[0] + 1, dtype=np.int64)
     np.cumsum(rl, out=row_ptr[1:])
-    return Slices(J, subj_ptr, row_ptr, np.concatenate(col_parts), np.concatenate(val_parts))
+    return Slices(J, subj_ptr, row_ptr, np.concatenate([q[2] for q in parts]),
+                  np.concatenate([q[3] for q in parts]))
 
 
-def _poisson_plus_one(lam):
-    def f(rng, n):
-        return 1 + rng.poisson(lam, size=n)
-    return f
+class _poisson_plus_one:
+    """1 + Poisson(lam) nonzeros per row."""
+
+    def __init__(self, lam):
+        self.lam = lam
+
+    def __call__(self, rng, n):
+        return 1 + rng.poisson(self.lam, size=n)
 
 
-def _uniform_int(lo, hi):
-    def f(rng, n):
-        return rng.integers(lo, hi + 1, size=n)
-    return f
+class _uniform_int:
+    """Uniform integer count in [lo, hi]."""
+
+    def __init__(self, lo, hi):
+        self.lo, self.hi = lo, hi
+
+    def __call__(self, rng, n):
+        return rng.integers(self.lo, self.hi + 1, size=n)
 
 
 # ---------------------------------------------------------------------------

@@ -163,6 +163,16 @@ enum {
 int parafac2_set_profiling(parafac2_ctx* c, int32_t on);
 int parafac2_get_profile(parafac2_ctx* c, double* ms, int64_t* launches);
 
+/* Launch configuration of this build (diagnostics for tests and tuning;
+ * touches no GPU).  kernel: 0 Procrustes step of the first iteration,
+ * 1 mode-3 / W update / next Procrustes step, 2 mode-2 scatter,
+ * 3 projection, 4 Q assembly.  threads receives the workgroup size,
+ * lds_bytes the dynamic LDS of one workgroup (for kernel 2 with the largest
+ * hot-column set, whose size goes to max_hot).  P2_ENOTSUP for an R that is
+ * not built. */
+int parafac2_launch_config(int32_t R, int32_t kernel, int32_t* threads, int64_t* lds_bytes,
+                           int32_t* max_hot);
+
 /* Release a context (the caller's buffers are not freed). */
 void parafac2_destroy(parafac2_ctx* c);
 

@@ -67,6 +67,7 @@ def load(path: str = LIB_PATH):
         "parafac2_get_q": (ctypes.c_int, [vp, i64, i64, vp]),
         "parafac2_set_profiling": (ctypes.c_int, [vp, i32]),
         "parafac2_get_profile": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int64)]),
+        "parafac2_launch_config": (ctypes.c_int, [i32, i32, P(i32), P(i64), P(i32)]),
         "parafac2_destroy": (None, [vp]),
         "parafac2_model_workspace_size": (ctypes.c_int, [i64, i32, P(sz)]),
         "parafac2_model_create": (ctypes.c_int, [P(vp), i64, i32, vp, vp, vp, sz, vp]),
@@ -85,7 +86,7 @@ def exported_symbols() -> list:
     return ["parafac2_abi_version", "parafac2_last_error", "parafac2_validate_host",
             "parafac2_workspace_size", "parafac2_init", "parafac2_iterate",
             "parafac2_get_mttkrp", "parafac2_get_q", "parafac2_set_profiling",
-            "parafac2_get_profile", "parafac2_destroy",
+            "parafac2_get_profile", "parafac2_launch_config", "parafac2_destroy",
             "parafac2_model_workspace_size", "parafac2_model_create", "parafac2_project",
             "parafac2_model_destroy"]
 
@@ -140,6 +141,16 @@ def parafac2_workspace_size(K: int, J: int, n_rows: int, nnz: int, R: int) -> in
     n = ctypes.c_size_t(0)
     _check(load().parafac2_workspace_size(ctypes.byref(c), R, None, ctypes.byref(n)))
     return n.value
+
+
+def parafac2_launch_config(R: int, kernel: int) -> tuple:
+    """(threads, lds_bytes, max_hot) of a kernel for rank R (no GPU)."""
+    t = ctypes.c_int32(0)
+    lds = ctypes.c_int64(0)
+    mh = ctypes.c_int32(0)
+    _check(load().parafac2_launch_config(R, kernel, ctypes.byref(t), ctypes.byref(lds),
+                                         ctypes.byref(mh)))
+    return t.value, lds.value, mh.value
 
 
 def parafac2_model_workspace_size(J: int, R: int) -> int:

@@ -535,6 +535,16 @@ int parafac2_get_profile(parafac2_ctx* c, double* ms, int64_t* launches) {
   return P2_OK;
 }
 
+int parafac2_launch_config(int32_t R, int32_t kernel, int32_t* threads, int64_t* lds_bytes,
+                           int32_t* max_hot) {
+  if (!p2::rank_supported(R)) return fail(P2_ENOTSUP, "R=%d is not built", R);
+  if (kernel < 0 || kernel > 4) return fail(P2_EINVAL, "kernel id %d", kernel);
+  if (threads) *threads = p2::launch_threads(R, kernel);
+  if (lds_bytes) *lds_bytes = (int64_t)p2::launch_lds(R, kernel);
+  if (max_hot) *max_hot = p2::mode2_max_hot(R);
+  return P2_OK;
+}
+
 void parafac2_destroy(parafac2_ctx* c) {
   if (!c) return;
   for (auto& e : c->events) {

@@ -36,6 +36,9 @@ hipError_t run_mode2(int R, const XEnc& X, int64_t K, const float* V, const floa
                      hipStream_t s);
 // Bytes of the per-block partial sums that run_mode2 writes.
 size_t mode2_part_bytes(int R, int64_t K, int hot);
+// Threads per block of a kernel (0 alpha, 1 gamma, 2 mode2, 3 project, 4 getq).
+int launch_threads(int R, int kernel);
+size_t launch_lds(int R, int kernel);
 hipError_t run_gram_tall(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s);
 hipError_t run_solve_h(int R, const double* M1, const double* WtW, const double* VtV, double* H,
                        double* HtH, double* N2p, const PolarParams& pp, hipStream_t s);

@@ -315,6 +315,11 @@ __global__ void __launch_bounds__(256) k_gamma(XEnc X, int64_t K, const float* _
 constexpr int kMode2Threads = 1024;
 
 template <int R>
+struct Mode2Lds {
+  static constexpr int kPerGroup = R * R;  // E_k (floats)
+};
+
+template <int R>
 __global__ void __launch_bounds__(kMode2Threads) k_mode2(XEnc X, int64_t K,
                                                           const float* __restrict__ V,
                                                           const float* __restrict__ W,
@@ -329,7 +334,7 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2(XEnc X, int64_t K,
   const int wave = threadIdx.x / kWave;
   const int groups_per_block = (blockDim.x / kWave) * GPW;
   float* shM2 = reinterpret_cast<float*>(p2_smem);  // hot x R
-  float* Es = shM2 + (size_t)hot * R + (wave * GPW + (L.live ? L.grp : 0)) * (R * R);
+  float* Es = shM2 + (size_t)hot * R + (wave * GPW + (L.live ? L.grp : 0)) * Mode2Lds<R>::kPerGroup;
   for (int i = threadIdx.x; i < hot * R; i += blockDim.x) shM2[i] = 0.f;
   __syncthreads();
 
@@ -997,12 +1002,7 @@ namespace p2 {
 namespace {
 
 constexpr int kMaxBlocks = 2048;
-constexpr int kLdsPerCu = 160 * 1024;
-
-template <int R>
-constexpr int block_threads() {
-  return R >= 32 ? 128 : 256;
-}
+constexpr size_t kLdsPerCu = 160 * 1024;  // bytes of LDS one workgroup may use on gfx950
 
 inline int grid_for(int64_t units, int per_block) {
   int64_t b = (units + per_block - 1) / per_block;
@@ -1013,12 +1013,67 @@ inline int grid_for(int64_t units, int per_block) {
 
 template <class Kern>
 hipError_t allow_lds(Kern k, size_t bytes) {
+  if (bytes > kLdsPerCu) return hipErrorInvalidConfiguration;  // never launch past the LDS
   if (bytes <= 64 * 1024) return hipSuccess;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Largest block (from `cands`, in wavefronts of 64) whose LDS, `shared` bytes
+// for the block plus `group` bytes per subject group, fits in `budget`; 0 if
+// none does.
+template <int R>
+constexpr int pick_threads(size_t shared, size_t group, size_t budget, int max_threads) {
+  for (int t = max_threads; t >= kWave; t /= 2) {
+    if (shared + (size_t)(t / kWave) * Geo<R>::GPW * group <= budget) return t;
+  }
+  return 0;
+}
+
+// LDS layout of each kernel: bytes shared by the block and bytes per group.
+template <int R> constexpr size_t alpha_shared() { return sizeof(double) * 2 * R * R; }
+template <int R> constexpr size_t alpha_group() { return sizeof(double) * PolarLds<R>::kPerGroup; }
+template <int R> constexpr size_t gamma_shared() { return sizeof(double) * (4 * R * R + 2); }
+template <int R> constexpr size_t gamma_group() { return sizeof(double) * PolarLds<R>::kPerGroup; }
+template <int R> constexpr size_t proj_shared() { return sizeof(double) * 3 * R * R; }
+template <int R> constexpr size_t proj_group() { return sizeof(double) * ProjLds<R>::kPerGroup; }
+template <int R> constexpr size_t getq_group() { return sizeof(float) * Geo<R>::NC * R; }
+template <int R> constexpr size_t mode2_group() { return sizeof(float) * Mode2Lds<R>::kPerGroup; }
+
+template <int R> constexpr int alpha_threads() {
+  return pick_threads<R>(alpha_shared<R>(), alpha_group<R>(), kLdsPerCu, 256);
+}
+template <int R> constexpr int gamma_threads() {
+  return pick_threads<R>(gamma_shared<R>(), gamma_group<R>(), kLdsPerCu, 256);
+}
+template <int R> constexpr int proj_threads() {
+  return pick_threads<R>(proj_shared<R>(), proj_group<R>(), kLdsPerCu, 256);
+}
+template <int R> constexpr int getq_threads() {
+  return pick_threads<R>(0, getq_group<R>(), kLdsPerCu, 256);
+}
+// mode 2: the per-group buffers may take at most half of the LDS, the hot
+// column partial sums take the rest
+template <int R> constexpr int mode2_threads() {
+  return pick_threads<R>(0, mode2_group<R>(), kLdsPerCu / 2, kMode2Threads);
+}
+template <int R> constexpr size_t mode2_groups_bytes() {
+  return (size_t)(mode2_threads<R>() / kWave) * Geo<R>::GPW * mode2_group<R>();
+}
+template <int R> constexpr int max_hot_t() {
+  return (int)((kLdsPerCu - 2048 - mode2_groups_bytes<R>()) / (sizeof(float) * R));
+}
+
 #define P2_RANKS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(32) X(40)
+
+// every built rank has a launch configuration that fits the LDS
+#define P2_CHECK_PLAN(r)                                                         \
+  static_assert(alpha_threads<r>() > 0 && gamma_threads<r>() > 0 &&              \
+                    proj_threads<r>() > 0 && getq_threads<r>() > 0 &&            \
+                    mode2_threads<r>() > 0 && max_hot_t<r>() >= 0,               \
+                "LDS plan does not fit for R=" #r);
+P2_RANKS(P2_CHECK_PLAN)
+#undef P2_CHECK_PLAN
 
 #define P2_DISPATCH(R, CALL)            \
   switch (R) {                          \
@@ -1041,9 +1096,9 @@ hipError_t allow_lds(Kern k, size_t bytes) {
 template <int R>
 hipError_t alpha_t(const XEnc& X, int64_t K, const float* V, const float* W, const double* H,
                    float* F, double* M1, const PolarParams& pp, hipStream_t s) {
-  constexpr int T = block_threads<R>();
+  constexpr int T = alpha_threads<R>();
   const int gpb = (T / kWave) * Geo<R>::GPW;
-  const size_t lds = sizeof(double) * (2 * R * R + (size_t)gpb * PolarLds<R>::kPerGroup);
+  const size_t lds = alpha_shared<R>() + (size_t)gpb * alpha_group<R>();
   hipError_t e = allow_lds(k_alpha<R>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_alpha<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V, W, H, F, M1,
@@ -1056,9 +1111,9 @@ hipError_t gamma_t(const XEnc& X, int64_t K, const float* V0, const float* V1, f
                    const double* H, const double* N3, const double* N3p, float* F, float* M3,
                    double* M1next, double* fitacc, int do_next, const PolarParams& pp,
                    hipStream_t s) {
-  constexpr int T = block_threads<R>();
+  constexpr int T = gamma_threads<R>();
   const int gpb = (T / kWave) * Geo<R>::GPW;
-  const size_t lds = sizeof(double) * (4 * R * R + 2 + (size_t)gpb * PolarLds<R>::kPerGroup);
+  const size_t lds = gamma_shared<R>() + (size_t)gpb * gamma_group<R>();
   hipError_t e = allow_lds(k_gamma<R>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gamma<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V0, V1, W, H, N3,
@@ -1067,29 +1122,21 @@ hipError_t gamma_t(const XEnc& X, int64_t K, const float* V0, const float* V1, f
 }
 
 template <int R>
-int mode2_group_floats() {
-  return (kMode2Threads / kWave) * Geo<R>::GPW * R * R;
+int mode2_blocks_t(int64_t K) {
+  const int gpb = (mode2_threads<R>() / kWave) * Geo<R>::GPW;
+  const int b = grid_for(K, gpb);
+  return b < 256 ? b : 256;
 }
-
-template <int R>
-int max_hot_t() {
-  // one 1024-thread block per CU: the hot partial sums take what the per-group
-  // E_k buffers leave of the LDS
-  const int budget = kLdsPerCu - mode2_group_floats<R>() * 4 - 2048;
-  return budget / (R * 4);
-}
-
-int mode2_blocks(int64_t K, int gpb) { return grid_for(K, gpb) < 256 ? grid_for(K, gpb) : 256; }
 
 template <int R>
 hipError_t mode2_t(const XEnc& X, int64_t K, const float* V, const float* W, const double* H,
                    const float* F, float* M2, float* part, int hot, hipStream_t s) {
-  constexpr int T = kMode2Threads;
-  const int gpb = (T / kWave) * Geo<R>::GPW;
-  const size_t lds = sizeof(float) * ((size_t)hot * R + mode2_group_floats<R>());
+  constexpr int T = mode2_threads<R>();
+  if (hot < 0 || hot > max_hot_t<R>()) return hipErrorInvalidValue;
+  const size_t lds = sizeof(float) * (size_t)hot * R + mode2_groups_bytes<R>();
   hipError_t e = allow_lds(k_mode2<R>, lds);
   if (e != hipSuccess) return e;
-  const int nb = mode2_blocks(K, gpb);
+  const int nb = mode2_blocks_t<R>(K);
   hipLaunchKernelGGL(k_mode2<R>, dim3(nb), dim3(T), lds, s, X, K, V, W, H, F, M2, part, hot);
   e = hipGetLastError();
   if (e != hipSuccess || hot == 0) return e;
@@ -1113,9 +1160,11 @@ hipError_t gram_tall_t(const float* A, int64_t n, int lda, double* out, hipStrea
 template <int R>
 hipError_t getq_t(const XEnc& X, int64_t k0, int64_t k1, const float* V, const float* F, float* Q,
                   int64_t row0, hipStream_t s) {
-  constexpr int T = block_threads<R>();
+  constexpr int T = getq_threads<R>();
   const int gpb = (T / kWave) * Geo<R>::GPW;
-  const size_t lds = sizeof(float) * (size_t)gpb * Geo<R>::NC * R;
+  const size_t lds = (size_t)gpb * getq_group<R>();
+  hipError_t e = allow_lds(k_getq<R>, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_getq<R>, dim3(grid_for(k1 - k0, gpb)), dim3(T), lds, s, X, k0, k1, V, F, Q,
                      row0);
   return hipGetLastError();
@@ -1125,9 +1174,9 @@ template <int R>
 hipError_t project_t(const XRaw& X, int64_t K, const float* V, const double* H, const double* N3,
                      const double* N3p, int n_steps, const float* w0, float* Qout, float* wout,
                      double* lossout, const PolarParams& pp, hipStream_t s) {
-  constexpr int T = block_threads<R>();
+  constexpr int T = proj_threads<R>();
   const int gpb = (T / kWave) * Geo<R>::GPW;
-  const size_t lds = sizeof(double) * (3 * R * R + (size_t)gpb * ProjLds<R>::kPerGroup);
+  const size_t lds = proj_shared<R>() + (size_t)gpb * proj_group<R>();
   hipError_t e = allow_lds(k_project<R>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_project<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V, H, N3, N3p,
@@ -1155,7 +1204,7 @@ bool rank_supported(int R) {
   }
 }
 
-int lds_bytes_per_cu() { return kLdsPerCu; }
+int lds_bytes_per_cu() { return (int)kLdsPerCu; }
 
 int mode2_max_hot(int R) {
   switch (R) {
@@ -1190,19 +1239,54 @@ hipError_t run_mode2(int R, const XEnc& X, int64_t K, const float* V, const floa
 }
 
 size_t mode2_part_bytes(int R, int64_t K, int hot) {
-  int gpw = 0;
+  if (hot <= 0) return 0;
   switch (R) {
 #define P2_CASE(r) \
   case r:          \
-    gpw = Geo<r>::GPW; \
-    break;
+    return sizeof(float) * (size_t)mode2_blocks_t<r>(K) * (size_t)hot * r;
     P2_RANKS(P2_CASE)
 #undef P2_CASE
     default:
       return 0;
   }
-  const int gpb = (kMode2Threads / kWave) * gpw;
-  return sizeof(float) * (size_t)mode2_blocks(K, gpb) * (size_t)hot * R;
+}
+
+size_t launch_lds(int R, int kernel) {
+  switch (R) {
+#define P2_CASE(r)                                                                          \
+  case r:                                                                                   \
+    switch (kernel) {                                                                       \
+      case 0: return alpha_shared<r>() + (size_t)(alpha_threads<r>() / kWave) * Geo<r>::GPW * alpha_group<r>(); \
+      case 1: return gamma_shared<r>() + (size_t)(gamma_threads<r>() / kWave) * Geo<r>::GPW * gamma_group<r>(); \
+      case 2: return sizeof(float) * (size_t)max_hot_t<r>() * r + mode2_groups_bytes<r>();  \
+      case 3: return proj_shared<r>() + (size_t)(proj_threads<r>() / kWave) * Geo<r>::GPW * proj_group<r>();    \
+      case 4: return (size_t)(getq_threads<r>() / kWave) * Geo<r>::GPW * getq_group<r>();   \
+      default: return 0;                                                                    \
+    }
+    P2_RANKS(P2_CASE)
+#undef P2_CASE
+    default:
+      return 0;
+  }
+}
+
+int launch_threads(int R, int kernel) {
+  switch (R) {
+#define P2_CASE(r)                                                           \
+  case r:                                                                    \
+    switch (kernel) {                                                        \
+      case 0: return alpha_threads<r>();                                     \
+      case 1: return gamma_threads<r>();                                     \
+      case 2: return mode2_threads<r>();                                     \
+      case 3: return proj_threads<r>();                                      \
+      case 4: return getq_threads<r>();                                      \
+      default: return 0;                                                     \
+    }
+    P2_RANKS(P2_CASE)
+#undef P2_CASE
+    default:
+      return 0;
+  }
 }
 
 hipError_t run_gram_tall(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s) {

@@ -1,0 +1,108 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function that
+include/parafac2.h declares, validates inputs on the host, and plans launches
+and workspaces that fit the hardware for every rank it is built for."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from datagen import gen_config
+from paper_1703_04219_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LDS_BYTES = 160 * 1024
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "parafac2.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(parafac2_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = B.load()
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(B.exported_symbols())
+    assert lib.parafac2_abi_version() == 1
+
+
+def test_validate_host_accepts_generated_input():
+    X, R = gen_config(1)
+    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, R)
+    assert rc == B.P2_OK and msg == ""
+
+
+def _mutated(field, fn):
+    X, R = gen_config(1)
+    arrs = dict(subj_ptr=X.subj_ptr.copy(), row_ptr=X.row_ptr.copy(), col=X.col.copy(),
+                val=X.val.copy())
+    fn(arrs[field])
+    return arrs, X.J, R
+
+
+@pytest.mark.parametrize("case,field,fn,code,text", [
+    ("col out of range", "col", lambda a: a.__setitem__(3, 100), B.P2_EINVAL, "out of range"),
+    ("negative col", "col", lambda a: a.__setitem__(3, -1), B.P2_EINVAL, "out of range"),
+    ("unsorted", "col", lambda a: a.__setitem__(slice(0, 2), a[0:2][::-1].copy()), B.P2_EINVAL,
+     "increasing"),
+    ("nan value", "val", lambda a: a.__setitem__(7, np.nan), B.P2_EINVAL, "non-finite"),
+    ("inf value", "val", lambda a: a.__setitem__(7, np.inf), B.P2_EINVAL, "non-finite"),
+])
+def test_validate_host_rejects_bad_input(case, field, fn, code, text):
+    arrs, J, R = _mutated(field, fn)
+    rc, msg = B.parafac2_validate_host(arrs["subj_ptr"], arrs["row_ptr"], arrs["col"],
+                                       arrs["val"], J, R)
+    assert rc == code, (case, msg)
+    assert text in msg
+
+
+def test_validate_host_rank_rules():
+    X, _ = gen_config(1)  # I_k in [5, 20]
+    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 6)
+    assert rc == B.P2_EINVAL and "I_k" in msg
+    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 7)
+    assert rc == B.P2_ENOTSUP
+    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 0)
+    assert rc == B.P2_EINVAL
+
+
+def test_validate_host_bad_offsets():
+    X, R = gen_config(1)
+    sp = X.subj_ptr.copy()
+    sp[-1] += 1
+    rc, _ = B.parafac2_validate_host(sp, X.row_ptr, X.col, X.val, X.J, R)
+    assert rc == B.P2_EINVAL
+    rp = X.row_ptr.copy()
+    rp[5], rp[6] = rp[6], rp[5]
+    rc, _ = B.parafac2_validate_host(X.subj_ptr, rp, X.col, X.val, X.J, R)
+    assert rc == B.P2_EINVAL
+
+
+@pytest.mark.parametrize("R", B.SUPPORTED_R)
+def test_launch_plans_fit_the_lds(R):
+    for kernel in range(5):
+        threads, lds, max_hot = B.parafac2_launch_config(R, kernel)
+        assert threads in (64, 128, 256, 512, 1024), (R, kernel, threads)
+        assert 0 < lds <= LDS_BYTES, (R, kernel, lds)
+        assert max_hot >= 0
+
+
+@pytest.mark.parametrize("R", B.SUPPORTED_R)
+def test_workspace_size_is_sane(R):
+    # K=1e6, J=5000, 55M rows, 63M nnz: encoded slices ~0.5 GB plus
+    # K*R*R*4 bytes of per-subject state, never wrapped around
+    n = B.parafac2_workspace_size(1_000_000, 5000, 55_000_000, 63_000_000, R)
+    base = 63_000_000 * 6 + 55_000_000 * 2
+    assert base + 1_000_000 * R * R * 4 <= n <= base + 1_000_000 * R * R * 4 + 2e9
+    small = B.parafac2_workspace_size(10, 50, 100, 300, R)
+    assert 0 < small < 64 * 2**20
+
+
+def test_launch_config_rejects_unbuilt_rank():
+    with pytest.raises(B.Parafac2Error) as e:
+        B.parafac2_launch_config(7, 0)
+    assert e.value.code == B.P2_ENOTSUP
