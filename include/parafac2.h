@@ -72,6 +72,28 @@ typedef struct {
   const float* val;        /* [nnz]      */
 } parafac2_csr;
 
+/* Launch schedule of the per-subject passes (the Procrustes step fused with
+ * mode 3, and the mode-2 scatter).  Subjects are independent within an
+ * iteration (Sec. "Methodology": the slice-wise MTTKRPs may be computed in any
+ * order), so the passes run over tiles -- ranges of subjects of one problem --
+ * in any order.  Tile lists are split into 8 contiguous bins, one per XCD.
+ * A zero-initialised struct selects the defaults. */
+typedef struct {
+  int32_t tile_rounds; /* subjects per Procrustes/mode-3 tile, in units of the
+                          subject groups that one workgroup holds; 0 -> 4      */
+  int32_t dynamic;     /* 0: static, workgroup b takes tiles b, b + grid, ...
+                          (all in the bin of its XCD); 1: workgroups take tiles
+                          from per-bin counters and move on to other bins when
+                          their own is used up                                 */
+  int32_t m2_tiles;    /* at most this many mode-2 tiles per problem (each
+                          writes one slot of hot-column partial sums); 0 ->
+                          the context's capacity                              */
+  int32_t graph;       /* 1: every iteration after the first Procrustes step
+                          replays a HIP graph captured once (per parity of the
+                          V buffers and per whether the next Procrustes step is
+                          fused in); 0: plain launches                        */
+} parafac2_sched;
+
 /* Options; a zero-initialised struct selects the defaults. */
 typedef struct {
   double tau_polar;  /* eigenvalues of G_k = B_k^T B_k (B_k = X_k V S_k H^T)
@@ -84,7 +106,10 @@ typedef struct {
   int32_t hot_cols;  /* columns whose mode-2 partial sums are kept in LDS;
                         0 -> as many as fit, -1 -> none                       */
   int32_t max_sweeps;/* cap on Jacobi sweeps per R x R eigenproblem; 0 -> 30 */
-  int32_t reserved[8];
+  parafac2_sched sched;  /* launch schedule of the context                    */
+  int32_t m2_capacity;   /* mode-2 partial-sum slots planned in the workspace
+                            (the largest m2_tiles a schedule may use); 0 -> 256 */
+  int32_t reserved[3];
 } parafac2_opts;
 
 /* ABI version of the loaded library (PARAFAC2_ABI_VERSION). */
@@ -173,8 +198,64 @@ int parafac2_get_profile(parafac2_ctx* c, double* ms, int64_t* launches);
 int parafac2_launch_config(int32_t R, int32_t kernel, int32_t* threads, int64_t* lds_bytes,
                            int32_t* max_hot);
 
+/* Replace the context's launch schedule (takes effect at the next iterate;
+ * captured graphs are dropped).  Synchronises the stream. */
+int parafac2_set_sched(parafac2_ctx* c, const parafac2_sched* sched);
+
+/* Time candidate schedules on real iterations of the context and keep the
+ * fastest: tile_rounds in {1, 2, 4, 8, 16} x {static, dynamic}, then m2_tiles
+ * in {16, 64, 256} (up to the capacity); the graph setting is kept.  Every
+ * trial runs iters_per_trial (>= 1) iterations, which advance the
+ * decomposition like parafac2_iterate.  chosen (host, or NULL) receives the
+ * schedule kept, best_ms (host, or NULL) its milliseconds per iteration. */
+int parafac2_autotune(parafac2_ctx* c, int32_t iters_per_trial, parafac2_sched* chosen,
+                      double* best_ms);
+
 /* Release a context (the caller's buffers are not freed). */
 void parafac2_destroy(parafac2_ctx* c);
+
+/* ---- batches of independent decompositions --------------------------------
+ * Not in the paper, which runs one problem at a time; it extends the paper's
+ * per-subject independence (Sec. "Methodology") to independent problems.  A
+ * batch drives n contexts (each made by parafac2_init, any mix of K, J and R)
+ * in lock step: every kernel of an iteration runs once per rank present in
+ * the batch, over the tiles of all its problems, instead of once per problem.
+ * The contexts must share the batch's stream and must all be at the same
+ * point: equal iteration parity and no context iterated on its own since the
+ * last batch call (else P2_ESTATE).  Contexts of one rank must have equal
+ * tau_polar, tau_pinv and max_sweeps.  A context may still be used on its own
+ * between batch calls (get_mttkrp, get_q, iterate), which moves it out of
+ * step until the others catch up. */
+typedef struct parafac2_batch parafac2_batch;
+
+/* Bytes of device workspace (descriptors, tile lists, counters) for a batch
+ * of these n contexts.  Touches no GPU. */
+int parafac2_batch_workspace_size(parafac2_ctx* const* ctxs, int32_t n, size_t* bytes);
+
+/* Create a batch over ctxs[0..n) (host array of handles, borrowed until
+ * parafac2_batch_destroy).  workspace: device, 256-byte aligned, at least
+ * parafac2_batch_workspace_size bytes.  sched may be NULL (defaults).
+ * Synchronises the stream once. */
+int parafac2_batch_create(parafac2_batch** out, parafac2_ctx* const* ctxs, int32_t n,
+                          void* workspace, size_t ws_bytes, void* stream,
+                          const parafac2_sched* sched);
+
+/* n_iters iterations of every context of the batch.  fit_host (host, or
+ * NULL) receives n_iters x n fits, entry [i * n + b] for iteration i of
+ * context b.  Each context's H, V, W are updated as by parafac2_iterate. */
+int parafac2_batch_iterate(parafac2_batch* b, int32_t n_iters, double* fit_host);
+
+int parafac2_batch_set_sched(parafac2_batch* b, const parafac2_sched* sched);
+
+/* As parafac2_autotune, over the whole batch. */
+int parafac2_batch_autotune(parafac2_batch* b, int32_t iters_per_trial, parafac2_sched* chosen,
+                            double* best_ms);
+
+/* Per-phase timing of batch iterations, as for a context. */
+int parafac2_batch_set_profiling(parafac2_batch* b, int32_t on);
+int parafac2_batch_get_profile(parafac2_batch* b, double* ms, int64_t* launches);
+
+void parafac2_batch_destroy(parafac2_batch* b);
 
 /* ---- projection of new subjects onto fixed (V, H) --------------------------
  * Not in the paper: it applies the subject-wise half of Algorithm

@@ -37,10 +37,19 @@ class Csr(ctypes.Structure):
                 ("val", ctypes.c_void_p)]
 
 
+class Sched(ctypes.Structure):
+    _fields_ = [("tile_rounds", ctypes.c_int32), ("dynamic", ctypes.c_int32),
+                ("m2_tiles", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("tau_polar", ctypes.c_double), ("tau_pinv", ctypes.c_double),
                 ("hot_cols", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("sched", Sched), ("m2_capacity", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -73,6 +82,16 @@ def load(path: str = LIB_PATH):
         "parafac2_model_create": (ctypes.c_int, [P(vp), i64, i32, vp, vp, vp, sz, vp]),
         "parafac2_project": (ctypes.c_int, [vp, P(Csr), i32, vp, vp, vp, vp, vp]),
         "parafac2_model_destroy": (None, [vp]),
+        "parafac2_set_sched": (ctypes.c_int, [vp, P(Sched)]),
+        "parafac2_autotune": (ctypes.c_int, [vp, i32, P(Sched), P(ctypes.c_double)]),
+        "parafac2_batch_workspace_size": (ctypes.c_int, [P(vp), i32, P(sz)]),
+        "parafac2_batch_create": (ctypes.c_int, [P(vp), P(vp), i32, vp, sz, vp, P(Sched)]),
+        "parafac2_batch_iterate": (ctypes.c_int, [vp, i32, P(ctypes.c_double)]),
+        "parafac2_batch_set_sched": (ctypes.c_int, [vp, P(Sched)]),
+        "parafac2_batch_autotune": (ctypes.c_int, [vp, i32, P(Sched), P(ctypes.c_double)]),
+        "parafac2_batch_set_profiling": (ctypes.c_int, [vp, i32]),
+        "parafac2_batch_get_profile": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int64)]),
+        "parafac2_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -88,7 +107,10 @@ def exported_symbols() -> list:
             "parafac2_get_mttkrp", "parafac2_get_q", "parafac2_set_profiling",
             "parafac2_get_profile", "parafac2_launch_config", "parafac2_destroy",
             "parafac2_model_workspace_size", "parafac2_model_create", "parafac2_project",
-            "parafac2_model_destroy"]
+            "parafac2_model_destroy", "parafac2_set_sched", "parafac2_autotune",
+            "parafac2_batch_workspace_size", "parafac2_batch_create", "parafac2_batch_iterate",
+            "parafac2_batch_set_sched", "parafac2_batch_autotune", "parafac2_batch_set_profiling",
+            "parafac2_batch_get_profile", "parafac2_batch_destroy"]
 
 
 def _check(rc: int):
@@ -106,9 +128,17 @@ def _stream_handle(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_opts(tau_polar=0.0, tau_pinv=0.0, hot_cols=0, max_sweeps=0) -> Opts:
+def make_sched(tile_rounds=0, dynamic=0, m2_tiles=0, graph=0) -> Sched:
+    return Sched(tile_rounds, dynamic, m2_tiles, graph)
+
+
+def make_opts(tau_polar=0.0, tau_pinv=0.0, hot_cols=0, max_sweeps=0, sched=None,
+              m2_capacity=0) -> Opts:
     o = Opts()
     o.tau_polar, o.tau_pinv, o.hot_cols, o.max_sweeps = tau_polar, tau_pinv, hot_cols, max_sweeps
+    if sched is not None:
+        o.sched = sched if isinstance(sched, Sched) else make_sched(**sched)
+    o.m2_capacity = m2_capacity
     return o
 
 
@@ -136,10 +166,13 @@ def parafac2_validate_host(subj_ptr, row_ptr, col, val, J: int, R: int) -> tuple
     return rc, buf.value.decode()
 
 
-def parafac2_workspace_size(K: int, J: int, n_rows: int, nnz: int, R: int) -> int:
+def parafac2_workspace_size(K: int, J: int, n_rows: int, nnz: int, R: int,
+                            opts: Optional[Opts] = None) -> int:
     c = Csr(K, J, n_rows, nnz, 0, 0, 0, 0)
     n = ctypes.c_size_t(0)
-    _check(load().parafac2_workspace_size(ctypes.byref(c), R, None, ctypes.byref(n)))
+    _check(load().parafac2_workspace_size(ctypes.byref(c), R,
+                                          ctypes.byref(opts) if opts is not None else None,
+                                          ctypes.byref(n)))
     return n.value
 
 
@@ -208,11 +241,12 @@ class Context:
         self.W = torch.as_tensor(W, dtype=torch.float32, device=dev).contiguous().clone()
         assert self.H.shape == (R, R) and self.V.shape == (X.J, R) and self.W.shape == (X.K, R)
         csr = X.csr()
-        self.ws_bytes = parafac2_workspace_size(csr.K, csr.J, csr.n_rows, csr.nnz, self.R)
+        self.opts = opts if opts is not None else make_opts()
+        self.ws_bytes = parafac2_workspace_size(csr.K, csr.J, csr.n_rows, csr.nnz, self.R,
+                                                self.opts)
         self._ws, wsp = _workspace(self.ws_bytes, dev)
         self.stream = stream
         h = ctypes.c_void_p(0)
-        self.opts = opts if opts is not None else make_opts()
         _check(self.lib.parafac2_init(ctypes.byref(h), ctypes.byref(csr), self.R, _ptr(self.H),
                                       _ptr(self.V), _ptr(self.W), wsp, self.ws_bytes,
                                       _stream_handle(stream), ctypes.byref(self.opts)))
@@ -251,9 +285,77 @@ class Context:
         _check(self.lib.parafac2_get_profile(self.handle, ms, n))
         return {p: (ms[i], n[i]) for i, p in enumerate(self.PHASES)}
 
+    def set_sched(self, sched: Sched):
+        _check(self.lib.parafac2_set_sched(self.handle, ctypes.byref(sched)))
+
+    def autotune(self, iters_per_trial: int = 2) -> tuple:
+        """(chosen Sched, ms per iteration); the trials advance the decomposition."""
+        sc = Sched()
+        ms = ctypes.c_double(0)
+        _check(self.lib.parafac2_autotune(self.handle, iters_per_trial, ctypes.byref(sc),
+                                          ctypes.byref(ms)))
+        return sc, ms.value
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.parafac2_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several contexts iterated in lock step (parafac2_batch_*)."""
+
+    def __init__(self, ctxs, sched: Optional[Sched] = None, stream=None):
+        import torch
+        self.lib = load()
+        self.ctxs = list(ctxs)  # keeps the contexts alive
+        n = len(self.ctxs)
+        self._arr = (ctypes.c_void_p * n)(*[c.handle.value for c in self.ctxs])
+        nb = ctypes.c_size_t(0)
+        _check(self.lib.parafac2_batch_workspace_size(self._arr, n, ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self._ws, wsp = _workspace(self.ws_bytes, self.ctxs[0].X.val.device)
+        h = ctypes.c_void_p(0)
+        _check(self.lib.parafac2_batch_create(ctypes.byref(h), self._arr, n, wsp, self.ws_bytes,
+                                              _stream_handle(stream),
+                                              ctypes.byref(sched) if sched is not None else None))
+        self.handle = h
+
+    def iterate(self, n: int, with_fit: bool = True) -> Optional[np.ndarray]:
+        """Fits as an (n, len(ctxs)) array (or None)."""
+        nc = len(self.ctxs)
+        fit = (ctypes.c_double * (n * nc))() if with_fit else None
+        _check(self.lib.parafac2_batch_iterate(self.handle, n, fit))
+        return np.array(fit[:], dtype=np.float64).reshape(n, nc) if with_fit else None
+
+    def set_sched(self, sched: Sched):
+        _check(self.lib.parafac2_batch_set_sched(self.handle, ctypes.byref(sched)))
+
+    def autotune(self, iters_per_trial: int = 2) -> tuple:
+        sc = Sched()
+        ms = ctypes.c_double(0)
+        _check(self.lib.parafac2_batch_autotune(self.handle, iters_per_trial, ctypes.byref(sc),
+                                                ctypes.byref(ms)))
+        return sc, ms.value
+
+    def set_profiling(self, on: bool):
+        _check(self.lib.parafac2_batch_set_profiling(self.handle, 1 if on else 0))
+
+    def profile(self) -> dict:
+        ms = (ctypes.c_double * 6)()
+        n = (ctypes.c_int64 * 6)()
+        _check(self.lib.parafac2_batch_get_profile(self.handle, ms, n))
+        return {p: (ms[i], n[i]) for i, p in enumerate(Context.PHASES)}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.parafac2_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -328,6 +430,26 @@ def parafac2_get_mttkrp(ctx: Context):
 
 def parafac2_get_q(ctx: Context, k0: int, k1: int):
     return ctx.q(k0, k1)
+
+
+def parafac2_set_sched(ctx: Context, sched: Sched):
+    return ctx.set_sched(sched)
+
+
+def parafac2_autotune(ctx: Context, iters_per_trial: int = 2):
+    return ctx.autotune(iters_per_trial)
+
+
+def parafac2_batch_create(ctxs, sched: Optional[Sched] = None, stream=None) -> Batch:
+    return Batch(ctxs, sched, stream)
+
+
+def parafac2_batch_iterate(batch: Batch, n_iters: int, with_fit: bool = True):
+    return batch.iterate(n_iters, with_fit)
+
+
+def parafac2_batch_autotune(batch: Batch, iters_per_trial: int = 2):
+    return batch.autotune(iters_per_trial)
 
 
 def parafac2_model_create(V, H, stream=None) -> Model:

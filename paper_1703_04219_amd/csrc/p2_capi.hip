@@ -1,27 +1,38 @@
 // Host runtime and C ABI of the PARAFAC2-ALS hot path (see include/parafac2.h).
 //
-// The context owns no device memory: every buffer is carved out of the
-// caller's workspace by a fixed plan (Plan below).  Init validates the input
-// on the device, relabels columns by decreasing frequency (hot columns get the
+// A context owns no device memory: every buffer is carved out of the caller's
+// workspace by a fixed plan (Plan below).  Init validates the input on the
+// device, relabels columns by decreasing frequency (hot columns get the
 // smallest ids, so the mode-2 kernel can keep their partial sums in LDS with a
 // single range test), re-encodes the slices compactly (16-bit columns, 16-bit
 // subject-relative row starts) and copies V into the internal column order.
+//
+// Iterations are driven by a Runner: launch groups of equal-rank problems,
+// each with a device array of problem descriptors and tile lists.  A context
+// has its own runner (a batch of one, arrays in its workspace); a batch has a
+// runner over many contexts (arrays in the batch workspace).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
 
 #include "../../include/parafac2.h"
+#include "p2_batch.h"
 #include "p2_device.h"
 #include "p2_kernels.h"
 
 namespace {
+
+using p2::kBins;
+using p2::kFitRing;
 
 thread_local std::string g_last_error;
 
@@ -36,33 +47,60 @@ int fail(int code, const char* fmt, ...) {
 }
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
-
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 inline int ldv_of(int R) { return (R + 3) & ~3; }
 
-constexpr int kFitRing = 1024;
+constexpr int kDefaultRounds = 4;
+constexpr int kDefaultM2Capacity = 256;
+constexpr int kMaxM2Capacity = 4096;
+
+int m2_capacity(const parafac2_opts* o) {
+  if (o && o->m2_capacity > 0) return std::min(o->m2_capacity, kMaxM2Capacity);
+  return kDefaultM2Capacity;
+}
+
+int hot_columns(const parafac2_opts* o, int R, int64_t J) {
+  const int maxhot = p2::mode2_max_hot(R);
+  if (o && o->hot_cols < 0) return 0;
+  if (o && o->hot_cols > 0) return (int)std::min<int64_t>({(int64_t)o->hot_cols, (int64_t)maxhot, J});
+  return (int)std::min<int64_t>(maxhot, J);
+}
+
+// Mode-2 partial-sum slots (tiles) of a problem of K subjects under a cap.
+int64_t mode2_parts(int64_t K, int R, int cap) {
+  const int64_t unit = std::max(1, p2::mode2_tile_unit(R));
+  return std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(K, unit)));
+}
 
 // Offsets of every piece of the context workspace.
 struct Plan {
-  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, V[2], F, M2, M2part, M3, small, err,
-      total;
-  // small block (doubles)
-  size_t oM1, oWtW, oVtV, oVtVraw, oHtH, oN2p, oN3, oN3p, oInv, oFitAcc, oNx2, oFits, nsmall;
+  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, V[2], F, M2, M3, small, err, part,
+      desc, tiles, m2tiles, tickets, iter, total;
+  int64_t cap_tiles = 0, cap_m2 = 0;  // tile capacities of the context's own runner
+  int m2cap = 0;                      // mode-2 partial-sum slots
+  int hot = 0;
 };
 
-Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R) {
+Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const parafac2_opts* o) {
   Plan p{};
   const int64_t LDV = ldv_of(R);
   size_t off = 0;
   auto take = [&](size_t bytes) {
-    const size_t o = off;
-    off = align_up(off + bytes);
-    return o;
+    const size_t at = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return at;
   };
+  p.hot = hot_columns(o, R, J);
+  p.m2cap = m2_capacity(o);
+  const int64_t nparts = mode2_parts(K, R, p.m2cap);
+  p.cap_tiles = round_up(ceil_div(K, std::max(1, p2::polar_tile_unit(R))), kBins);
+  p.cap_m2 = round_up(nparts, kBins);
   p.zbase = take(sizeof(int64_t) * (K + 1));
   p.rbase = take(sizeof(int64_t) * (K + 1));
-  p.rstart = take(sizeof(uint16_t) * (size_t)std::max<int64_t>(n_rows, 1));
-  p.col16 = take(sizeof(uint16_t) * (size_t)std::max<int64_t>(nnz, 1));
-  p.val = take(sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
+  p.rstart = take(sizeof(uint16_t) * (size_t)n_rows);
+  p.col16 = take(sizeof(uint16_t) * (size_t)nnz);
+  p.val = take(sizeof(float) * (size_t)nnz);
   p.rank = take(sizeof(int32_t) * J);
   p.perm = take(sizeof(int32_t) * J);
   p.hist = take(sizeof(uint32_t) * J);
@@ -70,25 +108,15 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R) {
   p.V[1] = take(sizeof(float) * J * LDV);
   p.F = take(sizeof(float) * (size_t)K * R * R);
   p.M2 = take(sizeof(float) * J * LDV);
-  p.M2part = take(p2::mode2_part_bytes(R, K, (int)std::min<int64_t>(p2::mode2_max_hot(R), J)));
   p.M3 = take(sizeof(float) * (size_t)K * R);
-  const size_t RR = (size_t)R * R;
-  size_t s = 0;
-  p.oM1 = s; s += RR;
-  p.oWtW = s; s += RR;
-  p.oVtV = s; s += RR;
-  p.oVtVraw = s; s += RR;
-  p.oHtH = s; s += RR;
-  p.oN2p = s; s += RR;
-  p.oN3 = s; s += RR;
-  p.oN3p = s; s += RR;
-  p.oInv = s; s += R;
-  p.oFitAcc = s; s += 2;
-  p.oNx2 = s; s += 1;
-  p.oFits = s; s += kFitRing;
-  p.nsmall = s;
-  p.small = take(sizeof(double) * s);
+  p.part = take(sizeof(float) * (size_t)nparts * p.hot * R);
+  p.small = take(sizeof(double) * p2::small_layout(R).total);
   p.err = take(sizeof(int) * 4);
+  p.desc = take(sizeof(p2::ProbDesc));
+  p.tiles = take(sizeof(p2::Tile) * (size_t)p.cap_tiles);
+  p.m2tiles = take(sizeof(p2::Tile) * (size_t)p.cap_m2);
+  p.tickets = take(sizeof(int) * p2::kTicketKinds * kBins);
+  p.iter = take(sizeof(int64_t));
   p.total = off;
   return p;
 }
@@ -105,11 +133,34 @@ p2::PolarParams polar_params(const parafac2_opts* o, int R) {
   return pp;
 }
 
+bool same_params(const p2::PolarParams& a, const p2::PolarParams& b) {
+  return a.tau_polar == b.tau_polar && a.tau_pinv == b.tau_pinv && a.max_sweeps == b.max_sweeps;
+}
+
+parafac2_sched normalized(const parafac2_sched* s) {
+  parafac2_sched r{};
+  if (s) r = *s;
+  if (r.tile_rounds <= 0) r.tile_rounds = kDefaultRounds;
+  r.tile_rounds = std::min(r.tile_rounds, 1 << 16);
+  r.dynamic = r.dynamic ? 1 : 0;
+  if (r.m2_tiles < 0) r.m2_tiles = 0;
+  r.graph = r.graph ? 1 : 0;
+  return r;
+}
+
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
     if (e_ != hipSuccess) return fail(P2_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+
+#define P2_TRY(expr)            \
+  do {                          \
+    const int rc_ = (expr);     \
+    if (rc_ != P2_OK) return rc_; \
+  } while (0)
+
+struct Runner;
 
 }  // namespace
 
@@ -130,6 +181,59 @@ struct parafac2_ctx {
   bool failed = false;
   int64_t iters_done = 0;
   std::vector<int64_t> subj_host;
+  Runner* own = nullptr;  // batch of one over this context
+
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  double* small() const { return at<double>(plan.small); }
+  float* V(int i) const { return at<float>(plan.V[i]); }
+  p2::ProbDesc desc() const {
+    p2::ProbDesc d{};
+    d.X = X;
+    d.K = K;
+    d.J = J;
+    d.V[0] = V(0);
+    d.V[1] = V(1);
+    d.W = W;
+    d.H = H;
+    d.F = at<float>(plan.F);
+    d.M2 = at<float>(plan.M2);
+    d.M3 = at<float>(plan.M3);
+    d.small = small();
+    d.iter = at<int64_t>(plan.iter);
+    d.part = at<float>(plan.part);
+    d.nparts = 0;  // set by the runner from its schedule
+    d.hot = hot;
+    return d;
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Runner: launch groups (one per rank) over a set of contexts
+// ---------------------------------------------------------------------------
+
+struct Group {
+  int R = 0;
+  std::vector<int> members;  // indices into Runner::ctxs
+  p2::PolarParams pp{};
+  p2::BatchView bv{};
+  p2::ProbDesc* desc = nullptr;  // device arrays (in the owner's workspace)
+  p2::Tile* tiles = nullptr;
+  p2::Tile* m2tiles = nullptr;
+  int* tickets = nullptr;
+  int64_t cap_tiles = 0, cap_m2 = 0;
+};
+
+struct Runner {
+  std::vector<parafac2_ctx*> ctxs;
+  std::vector<Group> groups;
+  parafac2_sched sched{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // capture stream of the graphs
+  hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  bool planned = false;
   // profiling: event pairs per phase, resolved lazily
   bool profiling = false;
   struct EvPair {
@@ -140,10 +244,438 @@ struct parafac2_ctx {
   double prof_ms[P2_NPHASES] = {0};
   int64_t prof_n[P2_NPHASES] = {0};
 
-  template <class T>
-  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-  double* small() const { return at<double>(plan.small); }
-  float* V(int i) const { return at<float>(plan.V[i]); }
+  ~Runner() {
+    drop_graphs();
+    for (auto& e : events) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  void drop_graphs() {
+    for (auto& row : exec)
+      for (auto& g : row) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
+};
+
+// Workspace bytes of a runner's arrays for these contexts, and the offsets.
+struct RunnerLayout {
+  struct G {
+    int R;
+    std::vector<int> members;
+    size_t desc, tiles, m2tiles, tickets;
+    int64_t cap_tiles, cap_m2;
+  };
+  std::vector<G> groups;
+  size_t total = 0;
+};
+
+RunnerLayout runner_layout(parafac2_ctx* const* ctxs, int n) {
+  RunnerLayout L;
+  std::map<int, std::vector<int>> by_rank;
+  for (int i = 0; i < n; ++i) by_rank[ctxs[i]->R].push_back(i);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  for (auto& kv : by_rank) {
+    RunnerLayout::G g;
+    g.R = kv.first;
+    g.members = kv.second;
+    const int unit = std::max(1, p2::polar_tile_unit(g.R));
+    int64_t nt = 0, nm = 0;
+    for (int i : g.members) {
+      nt += ceil_div(ctxs[i]->K, unit);
+      nm += mode2_parts(ctxs[i]->K, g.R, ctxs[i]->plan.m2cap);
+    }
+    g.cap_tiles = round_up(nt, kBins);
+    g.cap_m2 = round_up(nm, kBins);
+    g.desc = take(sizeof(p2::ProbDesc) * g.members.size());
+    g.tiles = take(sizeof(p2::Tile) * (size_t)g.cap_tiles);
+    g.m2tiles = take(sizeof(p2::Tile) * (size_t)g.cap_m2);
+    g.tickets = take(sizeof(int) * p2::kTicketKinds * kBins);
+    L.groups.push_back(g);
+  }
+  L.total = off;
+  return L;
+}
+
+// Spread a (problem, subject)-ordered tile sequence over kBins contiguous
+// bins of equal length (the last ones padded with empty tiles) and store them
+// bin-interleaved: position u * kBins + x holds tile u of bin x.
+std::vector<p2::Tile> bin_interleave(const std::vector<p2::Tile>& seq) {
+  const size_t n = seq.size();
+  const size_t per = std::max<size_t>(1, (n + kBins - 1) / kBins);
+  std::vector<p2::Tile> out(per * kBins, p2::Tile{0, 0, 0, 0});
+  for (size_t i = 0; i < n; ++i) out[(i % per) * kBins + i / per] = seq[i];
+  return out;
+}
+
+// Build descriptors and tile lists for the runner's schedule, upload them and
+// plan the launches.  Synchronises the stream.
+int runner_plan(Runner& r) {
+  r.drop_graphs();
+  r.planned = false;
+  for (Group& g : r.groups) {
+    const int unit = std::max(1, p2::polar_tile_unit(g.R));
+    const int64_t tile = (int64_t)unit * r.sched.tile_rounds;
+    std::vector<p2::ProbDesc> descs;
+    std::vector<p2::Tile> seq, m2seq;
+    int max_hot = 0;
+    int64_t maxK = 0, maxJ = 0;
+    for (size_t q = 0; q < g.members.size(); ++q) {
+      parafac2_ctx* c = r.ctxs[g.members[q]];
+      p2::ProbDesc d = c->desc();
+      int cap = c->plan.m2cap;
+      if (r.sched.m2_tiles > 0) cap = std::min(cap, r.sched.m2_tiles);
+      const int64_t nparts = mode2_parts(c->K, g.R, cap);
+      const int64_t per = ceil_div(c->K, nparts);
+      d.nparts = (int32_t)ceil_div(c->K, per);
+      descs.push_back(d);
+      for (int64_t k0 = 0; k0 < c->K; k0 += tile)
+        seq.push_back(p2::Tile{(int32_t)q, 0, k0, std::min(c->K, k0 + tile)});
+      for (int32_t sidx = 0; sidx < d.nparts; ++sidx) {
+        const int64_t k0 = (int64_t)sidx * per;
+        m2seq.push_back(p2::Tile{(int32_t)q, sidx, k0, std::min(c->K, k0 + per)});
+      }
+      max_hot = std::max(max_hot, c->hot);
+      maxK = std::max(maxK, c->K);
+      maxJ = std::max(maxJ, c->J);
+    }
+    const std::vector<p2::Tile> tiles = bin_interleave(seq);
+    const std::vector<p2::Tile> m2tiles = bin_interleave(m2seq);
+    if ((int64_t)tiles.size() > g.cap_tiles || (int64_t)m2tiles.size() > g.cap_m2 ||
+        tiles.size() > (size_t)INT_MAX / 2)
+      return fail(P2_EINVAL, "tile lists exceed the planned capacity");
+    HIP_TRY(hipMemcpyAsync(g.desc, descs.data(), sizeof(p2::ProbDesc) * descs.size(),
+                           hipMemcpyHostToDevice, r.stream));
+    HIP_TRY(hipMemcpyAsync(g.tiles, tiles.data(), sizeof(p2::Tile) * tiles.size(),
+                           hipMemcpyHostToDevice, r.stream));
+    HIP_TRY(hipMemcpyAsync(g.m2tiles, m2tiles.data(), sizeof(p2::Tile) * m2tiles.size(),
+                           hipMemcpyHostToDevice, r.stream));
+    HIP_TRY(hipStreamSynchronize(r.stream));  // the host vectors go out of scope
+    p2::BatchView& b = g.bv;
+    b = p2::BatchView{};
+    b.R = g.R;
+    b.np = (int)g.members.size();
+    b.desc = g.desc;
+    b.tiles = g.tiles;
+    b.ntiles = (int)tiles.size();
+    b.m2tiles = g.m2tiles;
+    b.nm2 = (int)m2tiles.size();
+    b.tickets = g.tickets;
+    b.dynamic = r.sched.dynamic;
+    b.max_hot = max_hot;
+    b.maxK = maxK;
+    b.maxJ = maxJ;
+    HIP_TRY(p2::plan_launch(b));
+  }
+  r.planned = true;
+  return P2_OK;
+}
+
+int runner_capture(Runner& r, int parity, int do_next);
+
+// Plan, then capture every graph the schedule will replay, so that no
+// capture happens inside a timed run.
+int runner_prepare(Runner& r) {
+  P2_TRY(runner_plan(r));
+  if (r.sched.graph)
+    for (int parity = 0; parity < 2; ++parity)
+      for (int dn = 0; dn < 2; ++dn) P2_TRY(runner_capture(r, parity, dn));
+  return P2_OK;
+}
+
+// Runs stmt (HIP_TRY'd launches) bracketed by events when profiling is on.
+#define PHASE(ph, stmt)                                                   \
+  do {                                                                    \
+    hipEvent_t ea_ = nullptr, eb_ = nullptr;                              \
+    if (prof) {                                                           \
+      HIP_TRY(hipEventCreate(&ea_));                                      \
+      HIP_TRY(hipEventCreate(&eb_));                                      \
+      HIP_TRY(hipEventRecord(ea_, s));                                    \
+    }                                                                     \
+    stmt;                                                                 \
+    if (prof) {                                                           \
+      HIP_TRY(hipEventRecord(eb_, s));                                    \
+      r.events.push_back({ph, ea_, eb_});                                 \
+    }                                                                     \
+  } while (0)
+
+// The Procrustes step and mode-1 partial sums of the first iteration of a run.
+int runner_alpha(Runner& r, int parity, hipStream_t s, bool prof) {
+  for (Group& g : r.groups) {
+    HIP_TRY(p2::run_reset_tickets(g.bv, s));
+    HIP_TRY(p2::run_zero(g.bv, 1, s));
+    PHASE(P2_PHASE_ALPHA, HIP_TRY(p2::run_alpha(g.bv, parity, g.pp, s)));
+  }
+  return P2_OK;
+}
+
+// One iteration after its Procrustes step: H, V and W updates, the fit and,
+// if do_next, the next Procrustes step.  Launches only (may be captured).
+int runner_body(Runner& r, int parity, int do_next, hipStream_t s, bool prof) {
+  for (Group& g : r.groups) {
+    const p2::BatchView& b = g.bv;
+    HIP_TRY(p2::run_reset_tickets(b, s));
+    HIP_TRY(p2::run_zero(b, 2 | 4 | 8 | 16, s));
+    // mode 1 -> H
+    PHASE(P2_PHASE_SOLVE_H, HIP_TRY(p2::run_gram(b, 0, parity, s));
+          HIP_TRY(p2::run_solve_h(b, g.pp, s)));
+    // mode 2 -> V
+    PHASE(P2_PHASE_MODE2, HIP_TRY(p2::run_mode2(b, parity, s)));
+    PHASE(P2_PHASE_VUPDATE, HIP_TRY(p2::run_vupdate(b, parity, s));
+          HIP_TRY(p2::run_gram(b, 1, parity, s)); HIP_TRY(p2::run_solve_n3(b, g.pp, s));
+          HIP_TRY(p2::run_vscale(b, parity, s)));
+    // mode 3 -> W, fit (+ next Procrustes step)
+    if (do_next) HIP_TRY(p2::run_zero(b, 1, s));
+    PHASE(P2_PHASE_GAMMA, HIP_TRY(p2::run_gamma(b, parity, do_next, g.pp, s)));
+    PHASE(P2_PHASE_FIT, HIP_TRY(p2::run_fit(b, s)));
+  }
+  return P2_OK;
+}
+
+int runner_capture(Runner& r, int parity, int do_next) {
+  if (!r.cap) HIP_TRY(hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(r.cap, hipStreamCaptureModeRelaxed));
+  const int rc = runner_body(r, parity, do_next, r.cap, false);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(r.cap, &graph);
+  if (rc != P2_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  HIP_TRY(e);
+  const hipError_t ei = hipGraphInstantiate(&r.exec[parity][do_next], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIP_TRY(ei);
+  return P2_OK;
+}
+
+int runner_check(Runner& r) {
+  parafac2_ctx* c0 = r.ctxs[0];
+  for (parafac2_ctx* c : r.ctxs) {
+    if (c->failed) return fail(P2_ESTATE, "a context is in a failed state");
+    if (c->cur != c0->cur || c->have_F != c0->have_F)
+      return fail(P2_ESTATE, "the contexts of the batch are not at the same point");
+  }
+  return P2_OK;
+}
+
+// n (<= kFitRing) iterations of every context of the runner.
+int runner_iterate_n(Runner& r, int32_t n, double* fit_host) {
+  if (!r.planned) P2_TRY(runner_prepare(r));
+  hipStream_t s = r.stream;
+  const bool prof = r.profiling;
+  const bool graph = r.sched.graph && !prof;
+  int parity = r.ctxs[0]->cur;
+  bool have_F = r.ctxs[0]->have_F;
+  int qv = -1;
+  for (int32_t it = 0; it < n; ++it) {
+    if (!have_F) P2_TRY(runner_alpha(r, parity, s, prof));
+    const int do_next = (it + 1 < n) ? 1 : 0;
+    if (graph) {
+      if (!r.exec[parity][do_next]) P2_TRY(runner_capture(r, parity, do_next));
+      HIP_TRY(hipGraphLaunch(r.exec[parity][do_next], s));
+    } else {
+      P2_TRY(runner_body(r, parity, do_next, s, prof));
+    }
+    qv = parity;
+    parity ^= 1;
+    have_F = do_next != 0;
+  }
+  for (parafac2_ctx* c : r.ctxs) {
+    c->cur = parity;
+    c->qv = qv;
+    c->have_F = have_F;
+    c->iters_done += n;
+    // publish V in the caller's column order
+    HIP_TRY(p2::run_permute_rows(c->V(c->cur), c->Vuser, c->J, c->R, c->LDV, c->R,
+                                 c->at<int32_t>(c->plan.perm), s));
+  }
+  if (fit_host) {
+    const int nc = (int)r.ctxs.size();
+    std::vector<double> tmp((size_t)n * nc);
+    for (int b = 0; b < nc; ++b) {
+      parafac2_ctx* c = r.ctxs[b];
+      const double* fits = c->small() + p2::small_layout(c->R).fits;
+      const int64_t first = (c->iters_done - n) % kFitRing;
+      const int64_t n1 = std::min<int64_t>(n, kFitRing - first);
+      HIP_TRY(hipMemcpyAsync(tmp.data() + (size_t)b * n, fits + first, sizeof(double) * n1,
+                             hipMemcpyDeviceToHost, s));
+      if (n1 < n)
+        HIP_TRY(hipMemcpyAsync(tmp.data() + (size_t)b * n + n1, fits, sizeof(double) * (n - n1),
+                               hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int b = 0; b < nc; ++b)
+      for (int32_t i = 0; i < n; ++i) fit_host[(size_t)i * nc + b] = tmp[(size_t)b * n + i];
+  }
+  return P2_OK;
+}
+
+int runner_iterate(Runner& r, int32_t n_iters, double* fit_host) {
+  if (n_iters < 0) return fail(P2_EINVAL, "n_iters < 0");
+  if (n_iters == 0) return P2_OK;
+  P2_TRY(runner_check(r));
+  const int nc = (int)r.ctxs.size();
+  int32_t done = 0;
+  while (done < n_iters) {
+    const int32_t n = std::min<int32_t>(n_iters - done, kFitRing);
+    const int rc = runner_iterate_n(r, n, fit_host ? fit_host + (size_t)done * nc : nullptr);
+    if (rc != P2_OK) {
+      for (parafac2_ctx* c : r.ctxs) c->failed = true;
+      return rc;
+    }
+    done += n;
+  }
+  return P2_OK;
+}
+
+int runner_set_sched(Runner& r, const parafac2_sched* sched) {
+  HIP_TRY(hipStreamSynchronize(r.stream));
+  r.sched = normalized(sched);
+  return runner_prepare(r);
+}
+
+// Coordinate search over the schedule, timed with events on real iterations.
+int runner_autotune(Runner& r, int32_t iters, parafac2_sched* chosen, double* best_ms) {
+  if (iters < 1) return fail(P2_EINVAL, "iters_per_trial must be >= 1");
+  P2_TRY(runner_check(r));
+  const bool prof = r.profiling;
+  r.profiling = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto trial = [&](const parafac2_sched& sc, double* ms) -> int {
+    P2_TRY(runner_set_sched(r, &sc));
+    P2_TRY(runner_iterate(r, 1, nullptr));  // warm: graphs captured, caches filled
+    HIP_TRY(hipEventRecord(e0, r.stream));
+    P2_TRY(runner_iterate(r, iters, nullptr));
+    HIP_TRY(hipEventRecord(e1, r.stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    *ms = (double)t / iters;
+    return P2_OK;
+  };
+  int rc = P2_OK;
+  parafac2_sched best = r.sched;
+  double best_t = 1e300;
+  const int rounds[] = {1, 2, 4, 8, 16};
+  for (int dyn = 0; dyn < 2 && rc == P2_OK; ++dyn)
+    for (int rd : rounds) {
+      parafac2_sched sc = best;
+      sc.tile_rounds = rd;
+      sc.dynamic = dyn;
+      double t = 0;
+      rc = trial(sc, &t);
+      if (rc != P2_OK) break;
+      if (t < best_t) {
+        best_t = t;
+        best = normalized(&sc);
+      }
+    }
+  int maxcap = 0;
+  for (parafac2_ctx* c : r.ctxs) maxcap = std::max(maxcap, c->plan.m2cap);
+  const int m2s[] = {16, 64, 256};
+  for (int m2 : m2s) {
+    if (rc != P2_OK) break;
+    if (m2 > maxcap) continue;
+    parafac2_sched sc = best;
+    sc.m2_tiles = m2;
+    double t = 0;
+    rc = trial(sc, &t);
+    if (rc != P2_OK) break;
+    if (t < best_t) {
+      best_t = t;
+      best = normalized(&sc);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  r.profiling = prof;
+  if (rc != P2_OK) return rc;
+  P2_TRY(runner_set_sched(r, &best));
+  if (chosen) *chosen = best;
+  if (best_ms) *best_ms = best_t;
+  return P2_OK;
+}
+
+int resolve_profile(Runner& r) {
+  if (r.events.empty()) return P2_OK;
+  HIP_TRY(hipStreamSynchronize(r.stream));
+  for (auto& e : r.events) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
+    r.prof_ms[e.phase] += ms;
+    r.prof_n[e.phase] += 1;
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  r.events.clear();
+  return P2_OK;
+}
+
+int runner_set_profiling(Runner& r, int32_t on) {
+  P2_TRY(resolve_profile(r));
+  r.profiling = on != 0;
+  for (int i = 0; i < P2_NPHASES; ++i) {
+    r.prof_ms[i] = 0.0;
+    r.prof_n[i] = 0;
+  }
+  return P2_OK;
+}
+
+int runner_get_profile(Runner& r, double* ms, int64_t* launches) {
+  P2_TRY(resolve_profile(r));
+  for (int i = 0; i < P2_NPHASES; ++i) {
+    if (ms) ms[i] = r.prof_ms[i];
+    if (launches) launches[i] = r.prof_n[i];
+  }
+  return P2_OK;
+}
+
+// Attach the layout's arrays (at base) to a new runner over ctxs.
+int runner_make(Runner** out, parafac2_ctx* const* ctxs, int n, const RunnerLayout& L,
+                unsigned char* base, hipStream_t s, const parafac2_sched* sched) {
+  auto* r = new Runner();
+  r->ctxs.assign(ctxs, ctxs + n);
+  r->stream = s;
+  r->sched = normalized(sched);
+  for (const auto& lg : L.groups) {
+    Group g;
+    g.R = lg.R;
+    g.members = lg.members;
+    g.pp = ctxs[lg.members[0]]->pp;
+    for (int i : lg.members)
+      if (!same_params(ctxs[i]->pp, g.pp)) {
+        delete r;
+        return fail(P2_EINVAL, "contexts of rank %d have different tau_polar/tau_pinv/max_sweeps",
+                    lg.R);
+      }
+    g.desc = reinterpret_cast<p2::ProbDesc*>(base + lg.desc);
+    g.tiles = reinterpret_cast<p2::Tile*>(base + lg.tiles);
+    g.m2tiles = reinterpret_cast<p2::Tile*>(base + lg.m2tiles);
+    g.tickets = reinterpret_cast<int*>(base + lg.tickets);
+    g.cap_tiles = lg.cap_tiles;
+    g.cap_m2 = lg.cap_m2;
+    r->groups.push_back(g);
+  }
+  *out = r;
+  return P2_OK;
+}
+
+}  // namespace
+
+struct parafac2_batch {
+  Runner* r = nullptr;
+  ~parafac2_batch() { delete r; }
 };
 
 struct parafac2_model {
@@ -244,12 +776,12 @@ int parafac2_validate_host(const parafac2_csr* host_X, int32_t R, char* msg, siz
   return rc;
 }
 
-int parafac2_workspace_size(const parafac2_csr* X, int32_t R, const parafac2_opts* /*opts*/,
+int parafac2_workspace_size(const parafac2_csr* X, int32_t R, const parafac2_opts* opts,
                             size_t* bytes) {
   if (!X || !bytes) return fail(P2_EINVAL, "NULL argument");
   if (R < 1 || X->K < 1 || X->J < 1 || X->n_rows < 0 || X->nnz < 0)
     return fail(P2_EINVAL, "bad sizes");
-  *bytes = make_plan(X->K, X->J, X->n_rows, X->nnz, R).total;
+  *bytes = make_plan(X->K, X->J, X->n_rows, X->nnz, R, opts).total;
   return P2_OK;
 }
 
@@ -266,7 +798,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   if (X->n_rows < X->K * (int64_t)R) return fail(P2_EINVAL, "n_rows < K*R: some I_k < R");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(P2_EINVAL, "workspace must be 256-byte aligned");
-  const Plan plan = make_plan(X->K, X->J, X->n_rows, X->nnz, R);
+  const Plan plan = make_plan(X->K, X->J, X->n_rows, X->nnz, R, opts);
   if (ws_bytes < plan.total)
     return fail(P2_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, plan.total);
 
@@ -284,15 +816,10 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   c->ws = reinterpret_cast<unsigned char*>(workspace);
   c->plan = plan;
   c->pp = polar_params(opts, R);
-  const int maxhot = p2::mode2_max_hot(R);
-  if (opts && opts->hot_cols < 0)
-    c->hot = 0;
-  else if (opts && opts->hot_cols > 0)
-    c->hot = (int)std::min<int64_t>({(int64_t)opts->hot_cols, (int64_t)maxhot, X->J});
-  else
-    c->hot = (int)std::min<int64_t>(maxhot, X->J);
+  c->hot = plan.hot;
 
   auto cleanup = [&](int rc) {
+    delete c->own;
     delete c;
     return rc;
   };
@@ -343,14 +870,16 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   INIT_TRY(hipMemcpyAsync(c->at<int32_t>(plan.rank), rank.data(), sizeof(int32_t) * X->J,
                           hipMemcpyHostToDevice, s));
   double* sm = c->small();
-  INIT_TRY(p2::run_fill_f64(sm, (int64_t)plan.nsmall, 0.0, s));
+  const p2::SmallLayout SL = p2::small_layout(R);
+  INIT_TRY(p2::run_fill_f64(sm, SL.total, 0.0, s));
+  INIT_TRY(p2::run_fill_f64(reinterpret_cast<double*>(c->at<int64_t>(plan.iter)), 1, 0.0, s));
   INIT_TRY(p2::run_encode(X->subj_ptr, X->row_ptr, X->col, X->val, X->K, X->nnz,
                           c->at<int32_t>(plan.rank), c->at<uint16_t>(plan.rstart),
-                          c->at<uint16_t>(plan.col16), c->at<float>(plan.val), sm + plan.oNx2, s));
+                          c->at<uint16_t>(plan.col16), c->at<float>(plan.val), sm + SL.nx2, s));
   INIT_TRY(p2::run_fill_f32(c->V(0), X->J * c->LDV, 0.f, s));
   INIT_TRY(p2::run_fill_f32(c->V(1), X->J * c->LDV, 0.f, s));
   INIT_TRY(p2::run_permute_rows(V, c->V(0), X->J, R, R, c->LDV, c->at<int32_t>(plan.rank), s));
-  INIT_TRY(p2::run_gram_tall(R, c->V(0), X->J, c->LDV, sm + plan.oVtV, s));
+  INIT_TRY(p2::run_gram_rows(R, c->V(0), X->J, c->LDV, sm + SL.VtV, s));
   INIT_TRY(hipStreamSynchronize(s));  // host vectors above go out of scope
   c->X.zbase = zbase;
   c->X.rbase = rbase;
@@ -359,112 +888,34 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   c->X.val = c->at<float>(plan.val);
   c->cur = 0;
   c->have_F = false;
+  {
+    RunnerLayout L;
+    RunnerLayout::G g;
+    g.R = R;
+    g.members = {0};
+    g.desc = plan.desc;
+    g.tiles = plan.tiles;
+    g.m2tiles = plan.m2tiles;
+    g.tickets = plan.tickets;
+    g.cap_tiles = plan.cap_tiles;
+    g.cap_m2 = plan.cap_m2;
+    L.groups.push_back(g);
+    parafac2_ctx* self = c;
+    const int rc = runner_make(&c->own, &self, 1, L, c->ws, s, opts ? &opts->sched : nullptr);
+    if (rc != P2_OK) return cleanup(rc);
+    const int rp = runner_prepare(*c->own);
+    if (rp != P2_OK) return cleanup(rp);
+  }
   *out = c;
   g_last_error.clear();
   return P2_OK;
 #undef INIT_TRY
 }
 
-// Runs stmt (a HIP_TRY'd launch) bracketed by events when profiling is on.
-#define PHASE(ph, stmt)                                                   \
-  do {                                                                    \
-    hipEvent_t ea_ = nullptr, eb_ = nullptr;                              \
-    if (c->profiling) {                                                   \
-      HIP_TRY(hipEventCreate(&ea_));                                      \
-      HIP_TRY(hipEventCreate(&eb_));                                      \
-      HIP_TRY(hipEventRecord(ea_, s));                                    \
-    }                                                                     \
-    stmt;                                                                 \
-    if (c->profiling) {                                                   \
-      HIP_TRY(hipEventRecord(eb_, s));                                    \
-      c->events.push_back({ph, ea_, eb_});                                \
-    }                                                                     \
-  } while (0)
-
-static int iterate_impl(parafac2_ctx* c, int32_t n_iters, double* fit_host) {
-  const Plan& P = c->plan;
-  hipStream_t s = c->stream;
-  const int R = c->R;
-  double* sm = c->small();
-  double* M1 = sm + P.oM1;
-  double* WtW = sm + P.oWtW;
-  double* VtV = sm + P.oVtV;
-  double* VtVraw = sm + P.oVtVraw;
-  double* HtH = sm + P.oHtH;
-  double* N2p = sm + P.oN2p;
-  double* N3 = sm + P.oN3;
-  double* N3p = sm + P.oN3p;
-  double* inv = sm + P.oInv;
-  double* fitacc = sm + P.oFitAcc;
-  double* nx2 = sm + P.oNx2;
-  double* fits = sm + P.oFits;
-  float* F = c->at<float>(P.F);
-  float* M2 = c->at<float>(P.M2);
-  float* M3 = c->at<float>(P.M3);
-  const int64_t RR = (int64_t)R * R;
-  for (int32_t it = 0; it < n_iters; ++it) {
-    float* Vc = c->V(c->cur);
-    float* Vn = c->V(1 - c->cur);
-    if (!c->have_F) {
-      HIP_TRY(p2::run_fill_f64(M1, RR, 0.0, s));
-      PHASE(P2_PHASE_ALPHA, HIP_TRY(p2::run_alpha(R, c->X, c->K, Vc, c->W, c->H, F, M1, c->pp, s)));
-    }
-    // mode 1 -> H
-    HIP_TRY(p2::run_fill_f64(WtW, RR, 0.0, s));
-    PHASE(P2_PHASE_SOLVE_H, HIP_TRY(p2::run_gram_tall(R, c->W, c->K, R, WtW, s));
-          HIP_TRY(p2::run_solve_h(R, M1, WtW, VtV, c->H, HtH, N2p, c->pp, s)));
-    // mode 2 -> V
-    HIP_TRY(p2::run_fill_f32(M2, c->J * c->LDV, 0.f, s));
-    PHASE(P2_PHASE_MODE2, HIP_TRY(p2::run_mode2(R, c->X, c->K, Vc, c->W, c->H, F, M2,
-                                                 c->at<float>(P.M2part), c->hot, s)));
-    PHASE(P2_PHASE_VUPDATE, HIP_TRY(p2::run_vupdate(R, M2, N2p, c->J, Vn, s));
-          HIP_TRY(p2::run_fill_f64(VtVraw, RR, 0.0, s));
-          HIP_TRY(p2::run_gram_tall(R, Vn, c->J, c->LDV, VtVraw, s));
-          HIP_TRY(p2::run_solve_n3(R, VtVraw, HtH, VtV, inv, N3, N3p, c->pp, s));
-          HIP_TRY(p2::run_vscale(R, Vn, c->J, inv, s)));
-    // mode 3 -> W, fit (+ next Procrustes step)
-    const int do_next = (it + 1 < n_iters) ? 1 : 0;
-    if (do_next) HIP_TRY(p2::run_fill_f64(M1, RR, 0.0, s));
-    HIP_TRY(p2::run_fill_f64(fitacc, 2, 0.0, s));
-    PHASE(P2_PHASE_GAMMA,
-          HIP_TRY(p2::run_gamma(R, c->X, c->K, Vc, Vn, c->W, c->H, N3, N3p, F, M3, M1, fitacc,
-                                do_next, c->pp, s)));
-    PHASE(P2_PHASE_FIT, HIP_TRY(p2::run_fit(fitacc, nx2, fits + (c->iters_done % kFitRing), s)));
-    c->qv = c->cur;
-    c->cur = 1 - c->cur;
-    c->have_F = do_next != 0;
-    c->iters_done++;
-  }
-  // publish V in the caller's column order
-  HIP_TRY(p2::run_permute_rows(c->V(c->cur), c->Vuser, c->J, R, c->LDV, R,
-                               c->at<int32_t>(P.perm), s));
-  if (fit_host) {
-    const int64_t first = c->iters_done - n_iters;
-    for (int32_t i = 0; i < n_iters; ++i) {
-      HIP_TRY(hipMemcpyAsync(fit_host + i, fits + ((first + i) % kFitRing), sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-    }
-    HIP_TRY(hipStreamSynchronize(s));
-  }
-  return P2_OK;
-}
-
 int parafac2_iterate(parafac2_ctx* c, int32_t n_iters, double* fit_host) {
   if (!c) return fail(P2_EINVAL, "ctx is NULL");
   if (c->failed) return fail(P2_ESTATE, "context is in a failed state");
-  if (n_iters < 0) return fail(P2_EINVAL, "n_iters < 0");
-  if (n_iters == 0) return P2_OK;
-  int32_t done = 0;
-  while (done < n_iters) {
-    const int32_t n = std::min<int32_t>(n_iters - done, kFitRing);
-    const int rc = iterate_impl(c, n, fit_host ? fit_host + done : nullptr);
-    if (rc != P2_OK) {
-      c->failed = true;
-      return rc;
-    }
-    done += n;
-  }
-  return P2_OK;
+  return runner_iterate(*c->own, n_iters, fit_host);
 }
 
 int parafac2_get_mttkrp(parafac2_ctx* c, double* M1, float* M2, float* M3) {
@@ -474,8 +925,8 @@ int parafac2_get_mttkrp(parafac2_ctx* c, double* M1, float* M2, float* M3) {
   const Plan& P = c->plan;
   hipStream_t s = c->stream;
   if (M1)
-    HIP_TRY(hipMemcpyAsync(M1, c->small() + P.oM1, sizeof(double) * c->R * c->R,
-                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(M1, c->small() + p2::small_layout(c->R).M1,
+                           sizeof(double) * c->R * c->R, hipMemcpyDeviceToDevice, s));
   if (M2)
     HIP_TRY(p2::run_permute_rows(c->at<float>(P.M2), M2, c->J, c->R, c->LDV, c->R,
                                  c->at<int32_t>(P.perm), s));
@@ -497,42 +948,27 @@ int parafac2_get_q(parafac2_ctx* c, int64_t k0, int64_t k1, float* Q) {
   return P2_OK;
 }
 
-static int resolve_profile(parafac2_ctx* c) {
-  if (c->events.empty()) return P2_OK;
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  for (auto& e : c->events) {
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
-    c->prof_ms[e.phase] += ms;
-    c->prof_n[e.phase] += 1;
-    (void)hipEventDestroy(e.a);
-    (void)hipEventDestroy(e.b);
-  }
-  c->events.clear();
-  return P2_OK;
-}
-
 int parafac2_set_profiling(parafac2_ctx* c, int32_t on) {
   if (!c) return fail(P2_EINVAL, "ctx is NULL");
-  const int rc = resolve_profile(c);
-  if (rc != P2_OK) return rc;
-  c->profiling = on != 0;
-  for (int i = 0; i < P2_NPHASES; ++i) {
-    c->prof_ms[i] = 0.0;
-    c->prof_n[i] = 0;
-  }
-  return P2_OK;
+  return runner_set_profiling(*c->own, on);
 }
 
 int parafac2_get_profile(parafac2_ctx* c, double* ms, int64_t* launches) {
   if (!c) return fail(P2_EINVAL, "ctx is NULL");
-  const int rc = resolve_profile(c);
-  if (rc != P2_OK) return rc;
-  for (int i = 0; i < P2_NPHASES; ++i) {
-    if (ms) ms[i] = c->prof_ms[i];
-    if (launches) launches[i] = c->prof_n[i];
-  }
-  return P2_OK;
+  return runner_get_profile(*c->own, ms, launches);
+}
+
+int parafac2_set_sched(parafac2_ctx* c, const parafac2_sched* sched) {
+  if (!c) return fail(P2_EINVAL, "ctx is NULL");
+  if (c->failed) return fail(P2_ESTATE, "context is in a failed state");
+  return runner_set_sched(*c->own, sched);
+}
+
+int parafac2_autotune(parafac2_ctx* c, int32_t iters_per_trial, parafac2_sched* chosen,
+                      double* best_ms) {
+  if (!c) return fail(P2_EINVAL, "ctx is NULL");
+  if (c->failed) return fail(P2_ESTATE, "context is in a failed state");
+  return runner_autotune(*c->own, iters_per_trial, chosen, best_ms);
 }
 
 int parafac2_launch_config(int32_t R, int32_t kernel, int32_t* threads, int64_t* lds_bytes,
@@ -547,12 +983,84 @@ int parafac2_launch_config(int32_t R, int32_t kernel, int32_t* threads, int64_t*
 
 void parafac2_destroy(parafac2_ctx* c) {
   if (!c) return;
-  for (auto& e : c->events) {
-    (void)hipEventDestroy(e.a);
-    (void)hipEventDestroy(e.b);
-  }
+  delete c->own;
   delete c;
 }
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+static int check_ctx_list(parafac2_ctx* const* ctxs, int32_t n) {
+  if (!ctxs || n < 1) return fail(P2_EINVAL, "need at least one context");
+  for (int32_t i = 0; i < n; ++i) {
+    if (!ctxs[i]) return fail(P2_EINVAL, "context %d is NULL", i);
+    for (int32_t j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(P2_EINVAL, "context %d appears twice", i);
+  }
+  return P2_OK;
+}
+
+int parafac2_batch_workspace_size(parafac2_ctx* const* ctxs, int32_t n, size_t* bytes) {
+  if (!bytes) return fail(P2_EINVAL, "NULL argument");
+  P2_TRY(check_ctx_list(ctxs, n));
+  *bytes = runner_layout(ctxs, n).total;
+  return P2_OK;
+}
+
+int parafac2_batch_create(parafac2_batch** out, parafac2_ctx* const* ctxs, int32_t n,
+                          void* workspace, size_t ws_bytes, void* stream,
+                          const parafac2_sched* sched) {
+  if (!out) return fail(P2_EINVAL, "out is NULL");
+  *out = nullptr;
+  P2_TRY(check_ctx_list(ctxs, n));
+  if (!workspace) return fail(P2_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(P2_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int32_t i = 0; i < n; ++i)
+    if (ctxs[i]->stream != s) return fail(P2_EINVAL, "context %d has another stream", i);
+  const RunnerLayout L = runner_layout(ctxs, n);
+  if (ws_bytes < L.total)
+    return fail(P2_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  auto* b = new parafac2_batch();
+  int rc = runner_make(&b->r, ctxs, n, L, reinterpret_cast<unsigned char*>(workspace), s, sched);
+  if (rc == P2_OK) rc = runner_prepare(*b->r);
+  if (rc != P2_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return P2_OK;
+}
+
+int parafac2_batch_iterate(parafac2_batch* b, int32_t n_iters, double* fit_host) {
+  if (!b) return fail(P2_EINVAL, "batch is NULL");
+  return runner_iterate(*b->r, n_iters, fit_host);
+}
+
+int parafac2_batch_set_sched(parafac2_batch* b, const parafac2_sched* sched) {
+  if (!b) return fail(P2_EINVAL, "batch is NULL");
+  return runner_set_sched(*b->r, sched);
+}
+
+int parafac2_batch_autotune(parafac2_batch* b, int32_t iters_per_trial, parafac2_sched* chosen,
+                            double* best_ms) {
+  if (!b) return fail(P2_EINVAL, "batch is NULL");
+  return runner_autotune(*b->r, iters_per_trial, chosen, best_ms);
+}
+
+int parafac2_batch_set_profiling(parafac2_batch* b, int32_t on) {
+  if (!b) return fail(P2_EINVAL, "batch is NULL");
+  return runner_set_profiling(*b->r, on);
+}
+
+int parafac2_batch_get_profile(parafac2_batch* b, double* ms, int64_t* launches) {
+  if (!b) return fail(P2_EINVAL, "batch is NULL");
+  return runner_get_profile(*b->r, ms, launches);
+}
+
+void parafac2_batch_destroy(parafac2_batch* b) { delete b; }
 
 // ---------------------------------------------------------------------------
 // projection model
@@ -624,7 +1132,7 @@ int parafac2_model_create(parafac2_model** out, int64_t J, int32_t R, const floa
   if ((e = hipMemcpyAsync(Hm, H, sizeof(double) * R * R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return bad(e, "copy H");
   if ((e = p2::run_fill_f64(VtV, (int64_t)R * R, 0.0, s)) != hipSuccess) return bad(e, "fill");
-  if ((e = p2::run_gram_tall(R, Vm, J, m->LDV, VtV, s)) != hipSuccess) return bad(e, "VtV");
+  if ((e = p2::run_gram_rows(R, Vm, J, m->LDV, VtV, s)) != hipSuccess) return bad(e, "VtV");
   if ((e = p2::run_model_prep(R, VtV, Hm, reinterpret_cast<double*>(m->ws + m->oHtH),
                               reinterpret_cast<double*>(m->ws + m->oN3),
                               reinterpret_cast<double*>(m->ws + m->oN3p), m->pp, s)) != hipSuccess)

@@ -8,6 +8,8 @@ namespace p2 {
 
 struct XEnc;
 struct XRaw;
+struct ProbDesc;
+struct Tile;
 
 struct PolarParams {
   double tau_polar;  // relative eigenvalue cut in G^{-1/2}
@@ -24,30 +26,47 @@ int lds_bytes_per_cu();
 // Largest number of hot columns whose mode-2 partial sums fit the LDS budget.
 int mode2_max_hot(int R);
 
-hipError_t run_alpha(int R, const XEnc& X, int64_t K, const float* V, const float* W,
-                     const double* H, float* F, double* M1, const PolarParams& pp,
-                     hipStream_t s);
-hipError_t run_gamma(int R, const XEnc& X, int64_t K, const float* V0, const float* V1, float* W,
-                     const double* H, const double* N3, const double* N3p, float* F, float* M3,
-                     double* M1next, double* fitacc, int do_next, const PolarParams& pp,
-                     hipStream_t s);
-hipError_t run_mode2(int R, const XEnc& X, int64_t K, const float* V, const float* W,
-                     const double* H, const float* F, float* M2, float* part, int hot,
-                     hipStream_t s);
-// Bytes of the per-block partial sums that run_mode2 writes.
-size_t mode2_part_bytes(int R, int64_t K, int hot);
+// One launch group: problems of one rank R whose per-iteration kernels run
+// together.  Every pointer is device memory.
+struct BatchView {
+  int R = 0, np = 0;
+  const ProbDesc* desc = nullptr;  // [np]
+  const Tile* tiles = nullptr;     // Procrustes / mode-3 tiles, ntiles % kBins == 0
+  int ntiles = 0;
+  const Tile* m2tiles = nullptr;   // mode-2 tiles, nm2 % kBins == 0
+  int nm2 = 0;
+  int* tickets = nullptr;          // kTicketKinds * kBins counters (dynamic schedule)
+  int dynamic = 0;
+  int max_hot = 0;                 // LDS hot columns of the mode-2 launch (max over problems)
+  int64_t maxK = 0, maxJ = 0;
+  // filled by plan_launch (needs the current device; nothing but launches
+  // happen afterwards, so the run_* calls below may be captured in a graph)
+  int grid_alpha = 0, grid_gamma = 0, grid_mode2 = 0;
+};
+
+// Subjects per Procrustes / mode-3 tile step (subject groups of one
+// workgroup), and per mode-2 workgroup round.
+int polar_tile_unit(int R);
+int mode2_tile_unit(int R);
 // Threads per block of a kernel (0 alpha, 1 gamma, 2 mode2, 3 project, 4 getq).
 int launch_threads(int R, int kernel);
 size_t launch_lds(int R, int kernel);
-hipError_t run_gram_tall(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s);
-hipError_t run_solve_h(int R, const double* M1, const double* WtW, const double* VtV, double* H,
-                       double* HtH, double* N2p, const PolarParams& pp, hipStream_t s);
-hipError_t run_vupdate(int R, const float* M2, const double* N2p, int64_t J, float* Vout,
-                       hipStream_t s);
-hipError_t run_solve_n3(int R, const double* VtVraw, const double* HtH, double* VtV,
-                        double* invnorm, double* N3, double* N3p, const PolarParams& pp,
-                        hipStream_t s);
-hipError_t run_vscale(int R, float* V, int64_t J, const double* invnorm, hipStream_t s);
+
+hipError_t plan_launch(BatchView& b);
+hipError_t run_alpha(const BatchView& b, int parity, const PolarParams& pp, hipStream_t s);
+hipError_t run_gamma(const BatchView& b, int parity, int do_next, const PolarParams& pp,
+                     hipStream_t s);
+hipError_t run_mode2(const BatchView& b, int parity, hipStream_t s);
+hipError_t run_gram(const BatchView& b, int which, int parity, hipStream_t s);
+hipError_t run_solve_h(const BatchView& b, const PolarParams& pp, hipStream_t s);
+hipError_t run_vupdate(const BatchView& b, int parity, hipStream_t s);
+hipError_t run_solve_n3(const BatchView& b, const PolarParams& pp, hipStream_t s);
+hipError_t run_vscale(const BatchView& b, int parity, hipStream_t s);
+// Zero per-problem accumulators: 1 M1, 2 W^T W, 4 V^T V raw, 8 fit terms, 16 M2.
+hipError_t run_zero(const BatchView& b, int mask, hipStream_t s);
+hipError_t run_fit(const BatchView& b, hipStream_t s);
+hipError_t run_reset_tickets(const BatchView& b, hipStream_t s);
+hipError_t run_gram_rows(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s);
 hipError_t run_getq(int R, const XEnc& X, int64_t k0, int64_t k1, const float* V, const float* F,
                     float* Q, int64_t row0, hipStream_t s);
 hipError_t run_project(int R, const XRaw& X, int64_t K, const float* V, const double* H,
@@ -72,6 +91,5 @@ hipError_t run_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t run_model_prep(int R, const double* VtV, const double* H, double* HtH, double* N3,
                           double* N3p, const PolarParams& pp, hipStream_t s);
 hipError_t run_iota(int32_t* p, int64_t n, hipStream_t s);
-hipError_t run_fit(const double* fitacc, const double* nx2, double* fit_out, hipStream_t s);
 
 }  // namespace p2

@@ -14,6 +14,7 @@
 //               next iteration's Procrustes step and mode-1 partial from
 //               C'_k = A'_k^T A'_k;
 //   k_fit       fit of the iteration.
+#include "p2_batch.h"
 #include "p2_device.h"
 #include "p2_kernels.h"
 
@@ -92,96 +93,158 @@ __device__ __forceinline__ void add_m1(double* shM1, const double (&y)[R], doubl
 }
 
 // ---------------------------------------------------------------------------
-// k_alpha: first Procrustes step of a run
+// Batches.  Every per-iteration kernel below runs over an array of problem
+// descriptors (ProbDesc, all of rank R) and, for the per-subject kernels, a
+// list of tiles (problem, subject range).  Blocks take tiles either in a
+// static order or from per-bin ticket counters in global memory (dynamic);
+// per-problem state that a block shares in LDS (H, N3, the mode-1 and fit
+// partial sums) is loaded and flushed per tile.  Empty (padding) tiles are
+// skipped.
+// ---------------------------------------------------------------------------
+
+// Tile index of this block's i-th claim, or -1 when there is none left.
+// Static (tickets == nullptr): tiles blockIdx.x, blockIdx.x + gridDim.x, ...;
+// with gridDim.x a multiple of kBins, every tile of a block lies in the bin of
+// the block's XCD.  Dynamic: the block takes the next tile of its own bin from
+// that bin's counter and, once the bin is used up, moves on to the following
+// bins.  sh[1] (bins used up so far) starts at 0.
+__device__ __forceinline__ int claim_tile(int ntiles, int* tickets, int i, int* sh) {
+  if (tickets == nullptr) {
+    const int t = blockIdx.x + i * gridDim.x;
+    return t < ntiles ? t : -1;
+  }
+  __syncthreads();  // every thread has read the previous claim
+  if (threadIdx.x == 0) {
+    int t = -1, b = sh[1];
+    const int x0 = blockIdx.x % kBins;
+    while (b < kBins) {
+      const int x = (x0 + b) % kBins;
+      const int tt = atomicAdd(&tickets[x], 1) * kBins + x;
+      if (tt < ntiles) {
+        t = tt;
+        break;
+      }
+      ++b;
+    }
+    sh[0] = t;
+    sh[1] = b;
+  }
+  __syncthreads();
+  return sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// k_alpha: the Procrustes step that starts a run of iterations.  Per subject:
+// A_k = X_k V (sparse gather, equation (mttkrp1_3)), C_k = A_k^T A_k (FP64),
+// F_k and (Y_k V) from the polar factor (objective (procrustes_obj)), mode-1
+// partial (Y_k V) S_k added into M1 (equation (mttkrp1_2)).
 // ---------------------------------------------------------------------------
 template <int R>
-__global__ void __launch_bounds__(256) k_alpha(XEnc X, int64_t K, const float* __restrict__ V,
-                                                const float* __restrict__ W,
-                                                const double* __restrict__ H, float* __restrict__ F,
-                                                double* __restrict__ M1, PolarParams pp) {
-  constexpr int NC = Geo<R>::NC;
+__global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
+                                                const Tile* __restrict__ T, int ntiles,
+                                                int* tickets, int parity, PolarParams pp) {
   constexpr int GPW = Geo<R>::GPW;
   constexpr int CH = PolarLds<R>::CH;
+  constexpr SmallLayout SL = small_layout(R);
+  __shared__ int sh_t[2];
+  if (threadIdx.x == 0) sh_t[1] = 0;
   const Lane L = lane_info<R>();
   const int wave = threadIdx.x / kWave;
-  const int groups_per_block = (blockDim.x / kWave) * GPW;
+  const int gpb = (blockDim.x / kWave) * GPW;
+  const int gslot = wave * GPW + (L.live ? L.grp : 0);
   double* Hs = reinterpret_cast<double*>(p2_smem);
   double* shM1 = Hs + R * R;
-  double* gbuf = shM1 + R * R + (wave * GPW + (L.live ? L.grp : 0)) * PolarLds<R>::kPerGroup;
+  double* gbuf = shM1 + R * R + gslot * PolarLds<R>::kPerGroup;
   double* region = gbuf;
   double* Cs = region;
   double* S = region + R * R;
   double* wv = gbuf + PolarLds<R>::kRegion;
   double* dl = wv + 2 * R;
-  load_shared_rxr<R>(Hs, H);
-  for (int i = threadIdx.x; i < R * R; i += blockDim.x) shM1[i] = 0.0;
-  __syncthreads();
-
   const int c = L.j;
-  if (L.live) {
-    const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
-    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
-    for (int64_t k = gid; k < K; k += stride) {
-      const Subj s = X.subj(k);
-      {
-        double crow[R];
+  for (int i = 0;; ++i) {
+    const int t = claim_tile(ntiles, tickets, i, sh_t);
+    if (t < 0) break;
+    const Tile tile = T[t];
+    if (tile.k0 >= tile.k1) continue;
+    const ProbDesc& D = P[tile.p];
+    const XEnc X = D.X;
+    const float* __restrict__ V = D.V[parity];
+    const float* __restrict__ W = D.W;
+    float* __restrict__ F = D.F;
+    __syncthreads();
+    load_shared_rxr<R>(Hs, D.H);
+    for (int q = threadIdx.x; q < R * R; q += blockDim.x) shM1[q] = 0.0;
+    __syncthreads();
+    if (L.live) {
+      for (int64_t k = tile.k0 + gslot; k < tile.k1; k += gpb) {
+        const Subj s = X.subj(k);
+        {
+          double crow[R];
 #pragma unroll
-        for (int l = 0; l < R; ++l) crow[l] = 0.0;
-        for (int i0 = 0; i0 < s.nrows; i0 += CH) {
-          const int n = min(CH, s.nrows - i0);
-          gather_rows<R>(X, s, i0, n, V, region, c);
-          wave_sync();
-          gram_accum<R>(region, region, n, c, crow);
-          wave_sync();
+          for (int l = 0; l < R; ++l) crow[l] = 0.0;
+          for (int i0 = 0; i0 < s.nrows; i0 += CH) {
+            const int n = min(CH, s.nrows - i0);
+            gather_rows<R>(X, s, i0, n, V, region, c);
+            wave_sync();
+            gram_accum<R>(region, region, n, c, crow);
+            wave_sync();
+          }
+          if (c < R) {
+#pragma unroll
+            for (int l = 0; l < R; ++l) Cs[c * R + l] = crow[l];
+            wv[c] = (double)W[k * R + c];
+          }
         }
+        wave_sync();
+        double f[R], y[R];
+        polar_rxr<R>(Cs, wv, Hs, S, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
+                     pp.max_sweeps, f, y);
         if (c < R) {
+          float* Fk = F + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
-          for (int l = 0; l < R; ++l) Cs[c * R + l] = crow[l];
-          wv[c] = (double)W[k * R + c];
+          for (int q = 0; q < R; ++q) Fk[q] = (float)f[q];
+          add_m1<R>(shM1, y, wv[c], c);
         }
+        wave_sync();
       }
-      wave_sync();
-      double f[R], y[R];
-      polar_rxr<R>(Cs, wv, Hs, S, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
-                   pp.max_sweeps, f, y);
-      if (c < R) {
-        float* Fk = F + (size_t)k * R * R + (size_t)c * R;
-#pragma unroll
-        for (int i = 0; i < R; ++i) Fk[i] = (float)f[i];
-        add_m1<R>(shM1, y, wv[c], c);
-      }
-      wave_sync();
+    }
+    __syncthreads();
+    double* M1 = D.small + SL.M1;
+    for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
+      const double v = shM1[q];
+      if (v != 0.0) atomicAdd(M1 + q, v);
     }
   }
-  block_reduce_atomic(shM1, R * R, M1);
 }
 
 // ---------------------------------------------------------------------------
-// k_gamma: mode 3 + W update + fit terms (+ next Procrustes step and mode 1)
+// k_gamma: mode-3 MTTKRP row per subject (equation (mttkrp3_row_wise)) from
+// A_k = X_k V_t and A'_k = X_k V_{t+1}: (Y_k V_{t+1}) = F_k A_k^T A'_k,
+// m3(c) = H(:, c) . (Y_k V_{t+1})(:, c); the W row update
+// w = m3 ((V^T V) * (H^T H))^+ (Algorithm "CP-ALS"); the loss terms; and, if
+// do_next, the next iteration's Procrustes step and mode-1 partial from
+// C'_k = A'_k^T A'_k.
 // ---------------------------------------------------------------------------
 template <int R>
-__global__ void __launch_bounds__(256) k_gamma(XEnc X, int64_t K, const float* __restrict__ V0,
-                                                const float* __restrict__ V1,
-                                                float* __restrict__ W,
-                                                const double* __restrict__ H,
-                                                const double* __restrict__ N3,
-                                                const double* __restrict__ N3p,
-                                                float* __restrict__ F, float* __restrict__ M3,
-                                                double* __restrict__ M1next,
-                                                double* __restrict__ fitacc, int do_next,
+__global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
+                                                const Tile* __restrict__ T, int ntiles,
+                                                int* tickets, int parity, int do_next,
                                                 PolarParams pp) {
-  constexpr int NC = Geo<R>::NC;
   constexpr int GPW = Geo<R>::GPW;
   constexpr int CH = PolarLds<R>::CH;
+  constexpr SmallLayout SL = small_layout(R);
+  __shared__ int sh_t[2];
+  if (threadIdx.x == 0) sh_t[1] = 0;
   const Lane L = lane_info<R>();
   const int wave = threadIdx.x / kWave;
-  const int groups_per_block = (blockDim.x / kWave) * GPW;
+  const int gpb = (blockDim.x / kWave) * GPW;
+  const int gslot = wave * GPW + (L.live ? L.grp : 0);
   double* Hs = reinterpret_cast<double*>(p2_smem);
   double* N3s = Hs + R * R;
   double* N3ps = N3s + R * R;
   double* shM1 = N3ps + R * R;
   double* shFit = shM1 + R * R;
-  double* gbuf = shFit + 2 + (wave * GPW + (L.live ? L.grp : 0)) * PolarLds<R>::kPerGroup;
+  double* gbuf = shFit + 2 + gslot * PolarLds<R>::kPerGroup;
   double* region = gbuf;
   double* A0 = region;
   double* A1 = region + CH * R;
@@ -190,115 +253,121 @@ __global__ void __launch_bounds__(256) k_gamma(XEnc X, int64_t K, const float* _
   double* wv = gbuf + PolarLds<R>::kRegion;
   double* mv = wv + R;
   double* dl = mv + R;
-  load_shared_rxr<R>(Hs, H);
-  load_shared_rxr<R>(N3s, N3);
-  load_shared_rxr<R>(N3ps, N3p);
-  for (int i = threadIdx.x; i < R * R + 2; i += blockDim.x) shM1[i] = 0.0;
-  __syncthreads();
-
   const int c = L.j;
   const bool real = c < R;
   const int cc = real ? c : 0;
-  double fa = 0.0, fb = 0.0;
-
-  if (L.live) {
-    const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
-    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
-    for (int64_t k = gid; k < K; k += stride) {
-      const Subj s = X.subj(k);
-      double crow[R];
-      {
-        double prow[R];
+  for (int i = 0;; ++i) {
+    const int t = claim_tile(ntiles, tickets, i, sh_t);
+    if (t < 0) break;
+    const Tile tile = T[t];
+    if (tile.k0 >= tile.k1) continue;
+    const ProbDesc& D = P[tile.p];
+    const XEnc X = D.X;
+    const float* __restrict__ V0 = D.V[parity];
+    const float* __restrict__ V1 = D.V[parity ^ 1];
+    float* __restrict__ W = D.W;
+    float* __restrict__ F = D.F;
+    float* __restrict__ M3 = D.M3;
+    __syncthreads();
+    load_shared_rxr<R>(Hs, D.H);
+    load_shared_rxr<R>(N3s, D.small + SL.N3);
+    load_shared_rxr<R>(N3ps, D.small + SL.N3p);
+    for (int q = threadIdx.x; q < R * R + 2; q += blockDim.x) shM1[q] = 0.0;
+    __syncthreads();
+    double fa = 0.0, fb = 0.0;
+    if (L.live) {
+      for (int64_t k = tile.k0 + gslot; k < tile.k1; k += gpb) {
+        const Subj s = X.subj(k);
+        double crow[R];
+        {
+          double prow[R];
 #pragma unroll
-        for (int l = 0; l < R; ++l) prow[l] = crow[l] = 0.0;
-        for (int i0 = 0; i0 < s.nrows; i0 += CH) {
-          const int n = min(CH, s.nrows - i0);
-          gather_rows2<R>(X, s, i0, n, V0, V1, A0, A1, c);
-          wave_sync();
-          gram_accum<R>(A0, A1, n, c, prow);  // row c of P = A^T A'
-          gram_accum<R>(A1, A1, n, c, crow);  // row c of C' = A'^T A'
-          wave_sync();
-        }
-        // F into LDS (column c), P row c into LDS
-        if (real) {
-          const float* Fk = F + (size_t)k * R * R + (size_t)c * R;
+          for (int l = 0; l < R; ++l) prow[l] = crow[l] = 0.0;
+          for (int i0 = 0; i0 < s.nrows; i0 += CH) {
+            const int n = min(CH, s.nrows - i0);
+            gather_rows2<R>(X, s, i0, n, V0, V1, A0, A1, c);
+            wave_sync();
+            gram_accum<R>(A0, A1, n, c, prow);  // row c of P = A^T A'
+            gram_accum<R>(A1, A1, n, c, crow);  // row c of C' = A'^T A'
+            wave_sync();
+          }
+          if (real) {
+            const float* Fk = F + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
-          for (int i = 0; i < R; ++i) SF[c * R + i] = (double)Fk[i];
+            for (int q = 0; q < R; ++q) SF[c * R + q] = (double)Fk[q];
 #pragma unroll
-          for (int l = 0; l < R; ++l) SP[c * R + l] = prow[l];
-        }
-      }
-      wave_sync();
-      // (Y V')(:, c) = F P(:, c);  m3(c) = H(:, c) . (Y V')(:, c)  (mttkrp3_row_wise)
-      double m3 = 0.0;
-      {
-        double yv[R];
-#pragma unroll
-        for (int i = 0; i < R; ++i) yv[i] = 0.0;
-#pragma nounroll
-        for (int l = 0; l < R; ++l) {
-          const double plc = SP[l * R + cc];
-#pragma unroll
-          for (int i = 0; i < R; ++i) yv[i] = fma(SF[l * R + i], plc, yv[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) m3 = fma(Hs[i * R + cc], yv[i], m3);
-      }
-      if (real) mv[c] = m3;
-      wave_sync();
-      // w_new(c) = sum_l m3(l) N3^+(l, c)
-      double wn = 0.0;
-#pragma unroll
-      for (int l = 0; l < R; ++l) wn = fma(mv[l], N3ps[l * R + cc], wn);
-      if (real) {
-        W[k * R + c] = (float)wn;
-        M3[k * R + c] = (float)m3;
-        wv[c] = (double)(float)wn;
-      }
-      wave_sync();
-      if (real) {
-        // loss terms <w, m3> and w^T N3 w, with w as stored
-        const double wf = wv[c];
-        double t = 0.0;
-#pragma unroll
-        for (int l = 0; l < R; ++l) t = fma(N3s[c * R + l], wv[l], t);
-        fa = fma(wf, m3, fa);
-        fb = fma(wf, t, fb);
-      }
-      if (do_next) {
-        // next Procrustes step from C' (stored over F) with H_{t+1} and w_{t+1}
-        if (real) {
-#pragma unroll
-          for (int l = 0; l < R; ++l) SF[c * R + l] = crow[l];
+            for (int l = 0; l < R; ++l) SP[c * R + l] = prow[l];
+          }
         }
         wave_sync();
-        double f[R], y[R];
-        polar_rxr<R>(SF, wv, Hs, SP, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
-                     pp.max_sweeps, f, y);
-        if (real) {
-          float* Fk = F + (size_t)k * R * R + (size_t)c * R;
+        double m3 = 0.0;
+        {
+          double yv[R];
 #pragma unroll
-          for (int i = 0; i < R; ++i) Fk[i] = (float)f[i];
-          add_m1<R>(shM1, y, wv[c], c);
+          for (int q = 0; q < R; ++q) yv[q] = 0.0;
+#pragma nounroll
+          for (int l = 0; l < R; ++l) {
+            const double plc = SP[l * R + cc];
+#pragma unroll
+            for (int q = 0; q < R; ++q) yv[q] = fma(SF[l * R + q], plc, yv[q]);
+          }
+#pragma unroll
+          for (int q = 0; q < R; ++q) m3 = fma(Hs[q * R + cc], yv[q], m3);
         }
+        if (real) mv[c] = m3;
+        wave_sync();
+        double wn = 0.0;
+#pragma unroll
+        for (int l = 0; l < R; ++l) wn = fma(mv[l], N3ps[l * R + cc], wn);
+        if (real) {
+          W[k * R + c] = (float)wn;
+          M3[k * R + c] = (float)m3;
+          wv[c] = (double)(float)wn;
+        }
+        wave_sync();
+        if (real) {
+          const double wf = wv[c];
+          double tt = 0.0;
+#pragma unroll
+          for (int l = 0; l < R; ++l) tt = fma(N3s[c * R + l], wv[l], tt);
+          fa = fma(wf, m3, fa);
+          fb = fma(wf, tt, fb);
+        }
+        if (do_next) {
+          if (real) {
+#pragma unroll
+            for (int l = 0; l < R; ++l) SF[c * R + l] = crow[l];
+          }
+          wave_sync();
+          double f[R], y[R];
+          polar_rxr<R>(SF, wv, Hs, SP, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
+                       pp.max_sweeps, f, y);
+          if (real) {
+            float* Fk = F + (size_t)k * R * R + (size_t)c * R;
+#pragma unroll
+            for (int q = 0; q < R; ++q) Fk[q] = (float)f[q];
+            add_m1<R>(shM1, y, wv[c], c);
+          }
+        }
+        wave_sync();
       }
-      wave_sync();
     }
-  }
-  if (L.live && real) {
-    atomicAdd(&shFit[0], fa);
-    atomicAdd(&shFit[1], fb);
-  }
-  __syncthreads();
-  if (do_next) {
-    for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
-      const double v = shM1[i];
-      if (v != 0.0) atomicAdd(M1next + i, v);
+    if (L.live && real) {
+      atomicAdd(&shFit[0], fa);
+      atomicAdd(&shFit[1], fb);
     }
-  }
-  if (threadIdx.x == 0) {
-    atomicAdd(fitacc + 0, shFit[0]);
-    atomicAdd(fitacc + 1, shFit[1]);
+    __syncthreads();
+    if (do_next) {
+      double* M1 = D.small + SL.M1;
+      for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
+        const double v = shM1[q];
+        if (v != 0.0) atomicAdd(M1 + q, v);
+      }
+    }
+    if (threadIdx.x == 0) {
+      atomicAdd(D.small + SL.fitacc + 0, shFit[0]);
+      atomicAdd(D.small + SL.fitacc + 1, shFit[1]);
+    }
   }
 }
 
@@ -308,9 +377,9 @@ __global__ void __launch_bounds__(256) k_gamma(XEnc X, int64_t K, const float* _
 // One lane per row: it gathers A(i, :) into registers, forms D(i, :) =
 // A(i, :) E_k with E_k staged in the group's LDS, and adds x_ij D(i, :) into
 // M2(j, :) -- in the block's LDS copy for the hot columns (ids < hot, the most
-// frequent after relabelling), with global atomics for the rest.  Each block
-// writes its hot partial sums to part[blockIdx] without atomics;
-// k_mode2_reduce adds them up.
+// frequent after relabelling), with global atomics for the rest.  Each tile
+// writes its hot partial sums, without atomics, to its own slot among its
+// problem's partial sums; k_mode2_reduce adds them up per problem.
 // ---------------------------------------------------------------------------
 constexpr int kMode2Threads = 1024;
 
@@ -320,121 +389,139 @@ struct Mode2Lds {
 };
 
 template <int R>
-__global__ void __launch_bounds__(kMode2Threads) k_mode2(XEnc X, int64_t K,
-                                                          const float* __restrict__ V,
-                                                          const float* __restrict__ W,
-                                                          const double* __restrict__ H,
-                                                          const float* __restrict__ F,
-                                                          float* __restrict__ M2,
-                                                          float* __restrict__ part, int hot) {
+__global__ void __launch_bounds__(kMode2Threads) k_mode2(const ProbDesc* __restrict__ P,
+                                                          const Tile* __restrict__ T, int ntiles,
+                                                          int* tickets, int parity,
+                                                          int max_hot) {
   constexpr int NC = Geo<R>::NC;
   constexpr int GPW = Geo<R>::GPW;
   constexpr int LDV = Geo<R>::LDV;
+  __shared__ int sh_t[2];
+  if (threadIdx.x == 0) sh_t[1] = 0;
   const Lane L = lane_info<R>();
   const int wave = threadIdx.x / kWave;
-  const int groups_per_block = (blockDim.x / kWave) * GPW;
-  float* shM2 = reinterpret_cast<float*>(p2_smem);  // hot x R
-  float* Es = shM2 + (size_t)hot * R + (wave * GPW + (L.live ? L.grp : 0)) * Mode2Lds<R>::kPerGroup;
-  for (int i = threadIdx.x; i < hot * R; i += blockDim.x) shM2[i] = 0.f;
-  __syncthreads();
-
+  const int gpb = (blockDim.x / kWave) * GPW;
+  const int gslot = wave * GPW + (L.live ? L.grp : 0);
+  float* shM2 = reinterpret_cast<float*>(p2_smem);  // up to max_hot x R
+  float* Es = shM2 + (size_t)max_hot * R + gslot * Mode2Lds<R>::kPerGroup;
   const int c = L.j;
   const bool real = c < R;
   const int cc = real ? c : 0;
-  if (L.live) {
-    float hc[R];
+  for (int i = 0;; ++i) {
+    const int t = claim_tile(ntiles, tickets, i, sh_t);
+    if (t < 0) break;
+    const Tile tile = T[t];
+    if (tile.k0 >= tile.k1) continue;
+    const ProbDesc& D = P[tile.p];
+    const XEnc X = D.X;
+    const float* __restrict__ V = D.V[parity];
+    const float* __restrict__ W = D.W;
+    const float* __restrict__ F = D.F;
+    float* __restrict__ M2 = D.M2;
+    const int hot = min(D.hot, max_hot);
+    __syncthreads();
+    for (int q = threadIdx.x; q < hot * R; q += blockDim.x) shM2[q] = 0.f;
+    __syncthreads();
+    if (L.live) {
+      float hc[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) hc[i] = (float)H[i * R + cc];
-    const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
-    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
-    for (int64_t k = gid; k < K; k += stride) {
-      const Subj s = X.subj(k);
-      {
-        // E(:, c) = w(c) F^T H(:, c), stored row-major E(p, c) = Es[p * R + c]
-        const float* Fk = F + (size_t)k * R * R;
-        const float wc = W[k * R + cc];
+      for (int q = 0; q < R; ++q) hc[q] = (float)D.H[q * R + cc];
+      for (int64_t k = tile.k0 + gslot; k < tile.k1; k += gpb) {
+        const Subj s = X.subj(k);
+        {
+          // E(:, c) = w(c) F^T H(:, c), stored row-major E(p, c) = Es[p * R + c]
+          const float* Fk = F + (size_t)k * R * R;
+          const float wc = W[k * R + cc];
 #pragma unroll
-        for (int p = 0; p < R; ++p) {
-          float t = 0.f;
+          for (int p = 0; p < R; ++p) {
+            float tt = 0.f;
 #pragma unroll
-          for (int i = 0; i < R; ++i) t = fmaf(Fk[p * R + i], hc[i], t);
-          if (real) Es[p * R + c] = t * wc;
+            for (int q = 0; q < R; ++q) tt = fmaf(Fk[p * R + q], hc[q], tt);
+            if (real) Es[p * R + c] = tt * wc;
+          }
         }
-      }
-      wave_sync();
+        wave_sync();
 #pragma nounroll
-      for (int ii = c; ii < s.nrows; ii += NC) {
-        int zs, ze;
-        X.row(s, ii, zs, ze);
-        float a[LDV];
+        for (int ii = c; ii < s.nrows; ii += NC) {
+          int zs, ze;
+          X.row(s, ii, zs, ze);
+          float a[LDV];
 #pragma unroll
-        for (int q = 0; q < LDV; ++q) a[q] = 0.f;
-        for (int z = zs; z < ze; ++z) {
-          const float x = X.valat(s, z);
-          const float4* vr = reinterpret_cast<const float4*>(V + (size_t)X.colat(s, z) * LDV);
+          for (int q = 0; q < LDV; ++q) a[q] = 0.f;
+          for (int z = zs; z < ze; ++z) {
+            const float x = X.valat(s, z);
+            const float4* vr = reinterpret_cast<const float4*>(V + (size_t)X.colat(s, z) * LDV);
 #pragma unroll
-          for (int q = 0; q < LDV / 4; ++q) {
-            const float4 t = vr[q];
-            a[4 * q + 0] = fmaf(x, t.x, a[4 * q + 0]);
-            a[4 * q + 1] = fmaf(x, t.y, a[4 * q + 1]);
-            a[4 * q + 2] = fmaf(x, t.z, a[4 * q + 2]);
-            a[4 * q + 3] = fmaf(x, t.w, a[4 * q + 3]);
+            for (int q = 0; q < LDV / 4; ++q) {
+              const float4 v4 = vr[q];
+              a[4 * q + 0] = fmaf(x, v4.x, a[4 * q + 0]);
+              a[4 * q + 1] = fmaf(x, v4.y, a[4 * q + 1]);
+              a[4 * q + 2] = fmaf(x, v4.z, a[4 * q + 2]);
+              a[4 * q + 3] = fmaf(x, v4.w, a[4 * q + 3]);
+            }
+          }
+          float d[R];
+#pragma unroll
+          for (int q = 0; q < R; ++q) d[q] = 0.f;
+#pragma unroll
+          for (int p = 0; p < R; ++p) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) d[q] = fmaf(a[p], Es[p * R + q], d[q]);
+          }
+          for (int z = zs; z < ze; ++z) {
+            const int j = X.colat(s, z);
+            const float x = X.valat(s, z);
+            if (j < hot) {
+              float* dst = shM2 + j * R;
+#pragma unroll
+              for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
+            } else {
+              float* dst = M2 + (size_t)j * LDV;
+#pragma unroll
+              for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
+            }
           }
         }
-        float d[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) d[q] = 0.f;
-#pragma unroll
-        for (int p = 0; p < R; ++p) {
-#pragma unroll
-          for (int q = 0; q < R; ++q) d[q] = fmaf(a[p], Es[p * R + q], d[q]);
-        }
-        for (int z = zs; z < ze; ++z) {
-          const int j = X.colat(s, z);
-          const float x = X.valat(s, z);
-          if (j < hot) {
-            float* dst = shM2 + j * R;
-#pragma unroll
-            for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
-          } else {
-            float* dst = M2 + (size_t)j * LDV;
-#pragma unroll
-            for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
-          }
-        }
+        wave_sync();
       }
-      wave_sync();
     }
+    __syncthreads();
+    float* mine = D.part + (int64_t)tile.slot * hot * R;
+    for (int q = threadIdx.x; q < hot * R; q += blockDim.x) mine[q] = shM2[q];
   }
-  __syncthreads();
-  float* mine = part + (size_t)blockIdx.x * hot * R;
-  for (int i = threadIdx.x; i < hot * R; i += blockDim.x) mine[i] = shM2[i];
 }
 
-// M2(j, :) += sum over blocks of part[b](j, :) for the hot columns
+// M2_p(j, :) += sum of the hot partial sums of problem p's mode-2 tiles;
+// grid.y = problem.
 template <int R>
-__global__ void __launch_bounds__(256) k_mode2_reduce(const float* __restrict__ part, int nblocks,
-                                                       int hot, float* __restrict__ M2) {
+__global__ void __launch_bounds__(256) k_mode2_reduce(const ProbDesc* __restrict__ P,
+                                                       int max_hot) {
   constexpr int LDV = Geo<R>::LDV;
+  const ProbDesc& D = P[blockIdx.y];
+  const int hot = min(D.hot, max_hot);
   const int n = hot * R;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+  const float* __restrict__ src = D.part;
+  float* __restrict__ M2 = D.M2;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     float acc = 0.f;
-    for (int b = 0; b < nblocks; ++b) acc += part[(size_t)b * n + t];
-    const int j = t / R, q = t - j * R;
-    M2[(size_t)j * LDV + q] += acc;
+    for (int t = 0; t < D.nparts; ++t) acc += src[(int64_t)t * n + q];
+    const int j = q / R, r = q - j * R;
+    M2[(size_t)j * LDV + r] += acc;
   }
 }
 
 // ---------------------------------------------------------------------------
-// tall-skinny Gram out(R x R, FP64) += A^T A for A (n x R, FP32, row stride lda)
+// Tall-skinny Gram out += A^T A (FP64) of an n x R float matrix with row
+// stride lda: a group of lanes per row, column c per lane, block partial sums
+// in LDS, one atomic per entry and block.
 // ---------------------------------------------------------------------------
 template <int R>
-__global__ void __launch_bounds__(256) k_gram_tall(const float* __restrict__ A, int64_t n,
-                                                    int lda, double* __restrict__ out) {
+__device__ void gram_rows(const float* __restrict__ A, int64_t n, int lda, double* out,
+                          int block, int nblocks) {
   constexpr int GPW = Geo<R>::GPW;
   const Lane L = lane_info<R>();
   const int wave = threadIdx.x / kWave;
-  const int groups_per_block = (blockDim.x / kWave) * GPW;
+  const int gpb = (blockDim.x / kWave) * GPW;
   double* sh = reinterpret_cast<double*>(p2_smem);
   for (int i = threadIdx.x; i < R * R; i += blockDim.x) sh[i] = 0.0;
   __syncthreads();
@@ -443,8 +530,8 @@ __global__ void __launch_bounds__(256) k_gram_tall(const float* __restrict__ A, 
     double acc[R];
 #pragma unroll
     for (int l = 0; l < R; ++l) acc[l] = 0.0;
-    const int64_t gid = (int64_t)blockIdx.x * groups_per_block + wave * GPW + L.grp;
-    const int64_t stride = (int64_t)gridDim.x * groups_per_block;
+    const int64_t gid = (int64_t)block * gpb + wave * GPW + L.grp;
+    const int64_t stride = (int64_t)nblocks * gpb;
     for (int64_t r = gid; r < n; r += stride) {
       const float* a = A + r * lda;
       const double ac = (double)a[c];
@@ -458,8 +545,29 @@ __global__ void __launch_bounds__(256) k_gram_tall(const float* __restrict__ A, 
   block_reduce_atomic(sh, R * R, out);
 }
 
+template <int R>
+__global__ void __launch_bounds__(256) k_gram_rows(const float* __restrict__ A, int64_t n,
+                                                    int lda, double* out) {
+  gram_rows<R>(A, n, lda, out, blockIdx.x, gridDim.x);
+}
+
+// Per problem (grid.y): which = 0: W^T W; 1: V_{t+1}^T V_{t+1} before
+// normalisation (into VtVraw); 2: V_t^T V_t (into VtV).
+template <int R>
+__global__ void __launch_bounds__(256) k_gram(const ProbDesc* __restrict__ P, int which,
+                                               int parity) {
+  constexpr SmallLayout SL = small_layout(R);
+  const ProbDesc& D = P[blockIdx.y];
+  if (which == 0)
+    gram_rows<R>(D.W, D.K, R, D.small + SL.WtW, blockIdx.x, gridDim.x);
+  else if (which == 1)
+    gram_rows<R>(D.V[parity ^ 1], D.J, Geo<R>::LDV, D.small + SL.VtVraw, blockIdx.x, gridDim.x);
+  else
+    gram_rows<R>(D.V[parity], D.J, Geo<R>::LDV, D.small + SL.VtV, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
-// small FP64 solves (one group of NC lanes)
+// small FP64 solves (one group of NC lanes per problem; grid = problems)
 // ---------------------------------------------------------------------------
 
 // Column c of N^+ for symmetric PSD N given column-per-lane (n = N(:, c)).
@@ -506,22 +614,25 @@ __device__ void pinv_cols(const double (&ncol)[R], int c, double* S, double* dl,
 // H <- M1 ((W^T W) * (V^T V))^+ (Algorithm "CP-ALS"), unit columns; H^T H;
 // N2^+ = ((W^T W) * (H^T H))^+.
 template <int R>
-__global__ void __launch_bounds__(64) k_solve_h(const double* __restrict__ M1,
-                                                 const double* __restrict__ WtW,
-                                                 const double* __restrict__ VtV,
-                                                 double* __restrict__ H, double* __restrict__ HtH,
-                                                 double* __restrict__ N2p, PolarParams pp) {
+__global__ void __launch_bounds__(64) k_solve_h(const ProbDesc* __restrict__ P, PolarParams pp) {
   constexpr int NC = Geo<R>::NC;
+  constexpr SmallLayout SL = small_layout(R);
   __shared__ double S[NC * R];
   __shared__ double dl[NC];
   __shared__ double Hs[R * R];
+  const ProbDesc& D = P[blockIdx.x];
+  const double* M1 = D.small + SL.M1;
+  const double* WtW = D.small + SL.WtW;
+  const double* VtV = D.small + SL.VtV;
+  double* HtH = D.small + SL.HtH;
+  double* N2p = D.small + SL.N2p;
+  double* H = D.H;
   const int c = threadIdx.x;
   const int cc = c < R ? c : 0;
   double ncol[R], np[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) ncol[i] = WtW[i * R + cc] * VtV[i * R + cc];
   pinv_cols<R>(ncol, c, S, dl, pp.tau_pinv, pp.tol, pp.max_sweeps, np);
-  // column c of H = M1 N1^+
   double h[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
@@ -535,6 +646,7 @@ __global__ void __launch_bounds__(64) k_solve_h(const double* __restrict__ M1,
   for (int i = 0; i < R; ++i) nrm = fma(h[i], h[i], nrm);
   nrm = sqrt(nrm);
   const double sc = nrm > 1e-300 ? 1.0 / nrm : 1.0;
+  __syncthreads();  // every lane has read M1 and the old H is no longer needed
   if (c < R) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -544,7 +656,6 @@ __global__ void __launch_bounds__(64) k_solve_h(const double* __restrict__ M1,
     }
   }
   __syncthreads();
-  // column c of H^T H and of N2 = (W^T W) * (H^T H)
 #pragma unroll
   for (int l = 0; l < R; ++l) {
     double t = 0.0;
@@ -560,13 +671,16 @@ __global__ void __launch_bounds__(64) k_solve_h(const double* __restrict__ M1,
   }
 }
 
-// V_raw(j, :) = M2(j, :) N2^+  (rows of stride LDV; padding stays zero)
+// V_raw(j, :) = M2(j, :) N2^+ into V_{t+1} (padding stays zero); grid.y = problem
 template <int R>
-__global__ void __launch_bounds__(256) k_vupdate(const float* __restrict__ M2,
-                                                  const double* __restrict__ N2p, int64_t J,
-                                                  float* __restrict__ Vout) {
+__global__ void __launch_bounds__(256) k_vupdate(const ProbDesc* __restrict__ P, int parity) {
   constexpr int LDV = Geo<R>::LDV;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < J;
+  constexpr SmallLayout SL = small_layout(R);
+  const ProbDesc& D = P[blockIdx.y];
+  const float* M2 = D.M2;
+  const double* N2p = D.small + SL.N2p;
+  float* Vout = D.V[parity ^ 1];
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < D.J;
        j += (int64_t)gridDim.x * blockDim.x) {
     double m[R];
 #pragma unroll
@@ -582,23 +696,25 @@ __global__ void __launch_bounds__(256) k_vupdate(const float* __restrict__ M2,
 }
 
 // Column norms of V_raw from its Gram, V^T V of the normalised V,
-// N3 = (V^T V) * (H^T H) and N3^+.
+// N3 = (V^T V) * (H^T H) and N3^+; grid = problems.
 template <int R>
-__global__ void __launch_bounds__(64) k_solve_n3(const double* __restrict__ VtVraw,
-                                                  const double* __restrict__ HtH,
-                                                  double* __restrict__ VtV,
-                                                  double* __restrict__ invnorm,
-                                                  double* __restrict__ N3,
-                                                  double* __restrict__ N3p, PolarParams pp) {
+__global__ void __launch_bounds__(64) k_solve_n3(const ProbDesc* __restrict__ P, PolarParams pp) {
   constexpr int NC = Geo<R>::NC;
+  constexpr SmallLayout SL = small_layout(R);
   __shared__ double S[NC * R];
   __shared__ double dl[NC];
   __shared__ double inv[R];
+  const ProbDesc& D = P[blockIdx.x];
+  const double* VtVraw = D.small + SL.VtVraw;
+  const double* HtH = D.small + SL.HtH;
+  double* VtV = D.small + SL.VtV;
+  double* invnorm = D.small + SL.inv;
+  double* N3 = D.small + SL.N3;
+  double* N3p = D.small + SL.N3p;
   const int c = threadIdx.x;
   const int cc = c < R ? c : 0;
   if (c < R) {
-    const double n2 = VtVraw[c * R + c];
-    const double nrm = sqrt(n2);
+    const double nrm = sqrt(VtVraw[c * R + c]);
     inv[c] = nrm > 1e-300 ? 1.0 / nrm : 1.0;
     invnorm[c] = inv[c];
   }
@@ -620,16 +736,63 @@ __global__ void __launch_bounds__(64) k_solve_n3(const double* __restrict__ VtVr
   }
 }
 
+// V_{t+1}(:, c) *= 1 / ||column c||; grid.y = problem
 template <int R>
-__global__ void __launch_bounds__(256) k_vscale(float* __restrict__ Vv, int64_t J,
-                                                 const double* __restrict__ invnorm) {
+__global__ void __launch_bounds__(256) k_vscale(const ProbDesc* __restrict__ P, int parity) {
   constexpr int LDV = Geo<R>::LDV;
-  const int64_t n = J * LDV;
+  constexpr SmallLayout SL = small_layout(R);
+  const ProbDesc& D = P[blockIdx.y];
+  float* Vv = D.V[parity ^ 1];
+  const double* invnorm = D.small + SL.inv;
+  const int64_t n = D.J * LDV;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(t % LDV);
     if (c < R) Vv[t] = (float)((double)Vv[t] * invnorm[c]);
   }
+}
+
+// Zero the per-iteration accumulators selected by mask (1 M1, 2 W^T W,
+// 4 V^T V raw, 8 fit terms, 16 M2); grid.y = problem.
+template <int R>
+__global__ void __launch_bounds__(256) k_zero(const ProbDesc* __restrict__ P, int mask) {
+  constexpr int LDV = Geo<R>::LDV;
+  constexpr SmallLayout SL = small_layout(R);
+  const ProbDesc& D = P[blockIdx.y];
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  if (mask & 1)
+    for (int q = tid; q < R * R; q += nth) D.small[SL.M1 + q] = 0.0;
+  if (mask & 2)
+    for (int q = tid; q < R * R; q += nth) D.small[SL.WtW + q] = 0.0;
+  if (mask & 4)
+    for (int q = tid; q < R * R; q += nth) D.small[SL.VtVraw + q] = 0.0;
+  if (mask & 8)
+    for (int q = tid; q < 2; q += nth) D.small[SL.fitacc + q] = 0.0;
+  if (mask & 16) {
+    const int64_t n = D.J * LDV;
+    for (int64_t q = tid; q < n; q += nth) D.M2[q] = 0.f;
+  }
+}
+
+// fit = 1 - loss / ||X||^2 into the ring slot of the iteration, which it
+// then counts as done; grid = problems
+template <int R>
+__global__ void k_fit(const ProbDesc* __restrict__ P) {
+  constexpr SmallLayout SL = small_layout(R);
+  if (threadIdx.x == 0) {
+    const ProbDesc& D = P[blockIdx.x];
+    const double* fa = D.small + SL.fitacc;
+    const double nx2 = D.small[SL.nx2];
+    const double loss = nx2 - 2.0 * fa[0] + fa[1];
+    const int64_t it = D.iter[0];
+    D.small[SL.fits + (int)(it % kFitRing)] = 1.0 - loss / nx2;
+    D.iter[0] = it + 1;
+  }
+}
+
+__global__ void k_fill_i32(int* __restrict__ p, int n, int v) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) p[q] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -984,14 +1147,6 @@ __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
     p[t] = v;
 }
 
-__global__ void k_fit(const double* __restrict__ fitacc, const double* __restrict__ nx2,
-                      double* __restrict__ fit_out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const double loss = nx2[0] - 2.0 * fitacc[0] + fitacc[1];
-    fit_out[0] = 1.0 - loss / nx2[0];
-  }
-}
-
 }  // namespace p2
 
 // ===========================================================================
@@ -1011,12 +1166,26 @@ inline int grid_for(int64_t units, int per_block) {
   return (int)b;
 }
 
+// LDS a plan may hand out as dynamic LDS: the CU's LDS less room for the few
+// words of static LDS some kernels declare (tile claims).
+constexpr size_t kStaticLdsRoom = 256;
+constexpr size_t kLdsBudget = kLdsPerCu - kStaticLdsRoom;
+
+// Refuse an LDS request that does not fit next to the kernel's static LDS;
+// above the default 64 KB, raise the kernel's dynamic-LDS cap to all that
+// is left (a cap, not a reservation: launches of the same kernel with other
+// sizes stay valid).
 template <class Kern>
 hipError_t allow_lds(Kern k, size_t bytes) {
-  if (bytes > kLdsPerCu) return hipErrorInvalidConfiguration;  // never launch past the LDS
-  if (bytes <= 64 * 1024) return hipSuccess;
+  hipFuncAttributes fa{};
+  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k));
+  if (e != hipSuccess) return e;
+  const size_t stat = fa.sharedSizeBytes;
+  if (stat > kStaticLdsRoom || bytes + stat > kLdsPerCu) return hipErrorInvalidConfiguration;
+  if (bytes + stat <= 64 * 1024) return hipSuccess;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(kLdsPerCu - stat));
 }
 
 // Largest block (from `cands`, in wavefronts of 64) whose LDS, `shared` bytes
@@ -1041,27 +1210,27 @@ template <int R> constexpr size_t getq_group() { return sizeof(float) * Geo<R>::
 template <int R> constexpr size_t mode2_group() { return sizeof(float) * Mode2Lds<R>::kPerGroup; }
 
 template <int R> constexpr int alpha_threads() {
-  return pick_threads<R>(alpha_shared<R>(), alpha_group<R>(), kLdsPerCu, 256);
+  return pick_threads<R>(alpha_shared<R>(), alpha_group<R>(), kLdsBudget, 256);
 }
 template <int R> constexpr int gamma_threads() {
-  return pick_threads<R>(gamma_shared<R>(), gamma_group<R>(), kLdsPerCu, 256);
+  return pick_threads<R>(gamma_shared<R>(), gamma_group<R>(), kLdsBudget, 256);
 }
 template <int R> constexpr int proj_threads() {
-  return pick_threads<R>(proj_shared<R>(), proj_group<R>(), kLdsPerCu, 256);
+  return pick_threads<R>(proj_shared<R>(), proj_group<R>(), kLdsBudget, 256);
 }
 template <int R> constexpr int getq_threads() {
-  return pick_threads<R>(0, getq_group<R>(), kLdsPerCu, 256);
+  return pick_threads<R>(0, getq_group<R>(), kLdsBudget, 256);
 }
 // mode 2: the per-group buffers may take at most half of the LDS, the hot
 // column partial sums take the rest
 template <int R> constexpr int mode2_threads() {
-  return pick_threads<R>(0, mode2_group<R>(), kLdsPerCu / 2, kMode2Threads);
+  return pick_threads<R>(0, mode2_group<R>(), kLdsBudget / 2, kMode2Threads);
 }
 template <int R> constexpr size_t mode2_groups_bytes() {
   return (size_t)(mode2_threads<R>() / kWave) * Geo<R>::GPW * mode2_group<R>();
 }
 template <int R> constexpr int max_hot_t() {
-  return (int)((kLdsPerCu - 2048 - mode2_groups_bytes<R>()) / (sizeof(float) * R));
+  return (int)((kLdsBudget - 2048 - mode2_groups_bytes<R>()) / (sizeof(float) * R));
 }
 
 #define P2_RANKS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(32) X(40)
@@ -1093,67 +1262,97 @@ P2_RANKS(P2_CHECK_PLAN)
     default: return hipErrorInvalidValue; \
   }
 
-template <int R>
-hipError_t alpha_t(const XEnc& X, int64_t K, const float* V, const float* W, const double* H,
-                   float* F, double* M1, const PolarParams& pp, hipStream_t s) {
-  constexpr int T = alpha_threads<R>();
-  const int gpb = (T / kWave) * Geo<R>::GPW;
-  const size_t lds = alpha_shared<R>() + (size_t)gpb * alpha_group<R>();
-  hipError_t e = allow_lds(k_alpha<R>, lds);
+template <int R> constexpr int polar_gpb() { return (gamma_threads<R>() / kWave) * Geo<R>::GPW; }
+template <int R> constexpr int mode2_gpb() { return (mode2_threads<R>() / kWave) * Geo<R>::GPW; }
+template <int R> constexpr size_t alpha_lds() {
+  return alpha_shared<R>() + (size_t)(alpha_threads<R>() / kWave) * Geo<R>::GPW * alpha_group<R>();
+}
+template <int R> constexpr size_t gamma_lds() {
+  return gamma_shared<R>() + (size_t)(gamma_threads<R>() / kWave) * Geo<R>::GPW * gamma_group<R>();
+}
+template <int R> size_t mode2_lds(int hot) {
+  return sizeof(float) * (size_t)hot * R + mode2_groups_bytes<R>();
+}
+
+int device_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return n;
+}
+
+// Workgroups of kernel k that fit on the device at once, rounded down to a
+// multiple of kBins (so a static schedule keeps every block in its XCD's bin)
+// and capped at `want` rounded up the same way.
+template <class Kern>
+hipError_t resident_grid(Kern k, int threads, size_t lds, int want, int* grid) {
+  hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_alpha<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V, W, H, F, M1,
-                     pp);
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k),
+                                                   threads, lds);
+  if (e != hipSuccess) return e;
+  const int cus = device_cus();
+  if (per_cu < 1 || cus < 1) return hipErrorInvalidConfiguration;
+  int g = per_cu * cus / kBins * kBins;
+  if (g < kBins) g = kBins;
+  const int w = (want + kBins - 1) / kBins * kBins;
+  if (w > 0 && g > w) g = w;
+  *grid = g;
+  return hipSuccess;
+}
+
+template <int R>
+hipError_t plan_t(BatchView& b) {
+  if (b.ntiles % kBins != 0 || b.nm2 % kBins != 0) return hipErrorInvalidValue;
+  if (b.max_hot < 0 || b.max_hot > max_hot_t<R>()) return hipErrorInvalidValue;
+  hipError_t e = resident_grid(k_alpha<R>, alpha_threads<R>(), alpha_lds<R>(), b.ntiles,
+                               &b.grid_alpha);
+  if (e != hipSuccess) return e;
+  e = resident_grid(k_gamma<R>, gamma_threads<R>(), gamma_lds<R>(), b.ntiles, &b.grid_gamma);
+  if (e != hipSuccess) return e;
+  return resident_grid(k_mode2<R>, mode2_threads<R>(), mode2_lds<R>(b.max_hot), b.nm2,
+                       &b.grid_mode2);
+}
+
+inline int* tickets_of(const BatchView& b, int kind) {
+  return b.dynamic ? b.tickets + kind * kBins : nullptr;
+}
+
+template <int R>
+hipError_t alpha_t(const BatchView& b, int parity, const PolarParams& pp, hipStream_t s) {
+  hipLaunchKernelGGL(k_alpha<R>, dim3(b.grid_alpha), dim3(alpha_threads<R>()), alpha_lds<R>(), s,
+                     b.desc, b.tiles, b.ntiles, tickets_of(b, kTicketAlpha), parity, pp);
   return hipGetLastError();
 }
 
 template <int R>
-hipError_t gamma_t(const XEnc& X, int64_t K, const float* V0, const float* V1, float* W,
-                   const double* H, const double* N3, const double* N3p, float* F, float* M3,
-                   double* M1next, double* fitacc, int do_next, const PolarParams& pp,
+hipError_t gamma_t(const BatchView& b, int parity, int do_next, const PolarParams& pp,
                    hipStream_t s) {
-  constexpr int T = gamma_threads<R>();
-  const int gpb = (T / kWave) * Geo<R>::GPW;
-  const size_t lds = gamma_shared<R>() + (size_t)gpb * gamma_group<R>();
-  hipError_t e = allow_lds(k_gamma<R>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gamma<R>, dim3(grid_for(K, gpb)), dim3(T), lds, s, X, K, V0, V1, W, H, N3,
-                     N3p, F, M3, M1next, fitacc, do_next, pp);
+  hipLaunchKernelGGL(k_gamma<R>, dim3(b.grid_gamma), dim3(gamma_threads<R>()), gamma_lds<R>(), s,
+                     b.desc, b.tiles, b.ntiles, tickets_of(b, kTicketGamma), parity, do_next, pp);
   return hipGetLastError();
 }
 
 template <int R>
-int mode2_blocks_t(int64_t K) {
-  const int gpb = (mode2_threads<R>() / kWave) * Geo<R>::GPW;
-  const int b = grid_for(K, gpb);
-  return b < 256 ? b : 256;
-}
-
-template <int R>
-hipError_t mode2_t(const XEnc& X, int64_t K, const float* V, const float* W, const double* H,
-                   const float* F, float* M2, float* part, int hot, hipStream_t s) {
-  constexpr int T = mode2_threads<R>();
-  if (hot < 0 || hot > max_hot_t<R>()) return hipErrorInvalidValue;
-  const size_t lds = sizeof(float) * (size_t)hot * R + mode2_groups_bytes<R>();
-  hipError_t e = allow_lds(k_mode2<R>, lds);
-  if (e != hipSuccess) return e;
-  const int nb = mode2_blocks_t<R>(K);
-  hipLaunchKernelGGL(k_mode2<R>, dim3(nb), dim3(T), lds, s, X, K, V, W, H, F, M2, part, hot);
-  e = hipGetLastError();
-  if (e != hipSuccess || hot == 0) return e;
-  const int n = hot * R;
-  int rb = (n + 255) / 256;
+hipError_t mode2_t(const BatchView& b, int parity, hipStream_t s) {
+  hipLaunchKernelGGL(k_mode2<R>, dim3(b.grid_mode2), dim3(mode2_threads<R>()),
+                     mode2_lds<R>(b.max_hot), s, b.desc, b.m2tiles, b.nm2,
+                     tickets_of(b, kTicketMode2), parity, b.max_hot);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || b.max_hot == 0) return e;
+  int rb = (b.max_hot * R + 255) / 256;
   if (rb > 1024) rb = 1024;
-  hipLaunchKernelGGL(k_mode2_reduce<R>, dim3(rb), dim3(256), 0, s, part, nb, hot, M2);
+  hipLaunchKernelGGL(k_mode2_reduce<R>, dim3(rb, b.np), dim3(256), 0, s, b.desc, b.max_hot);
   return hipGetLastError();
 }
 
 template <int R>
-hipError_t gram_tall_t(const float* A, int64_t n, int lda, double* out, hipStream_t s) {
-  constexpr int T = 256;
-  const int gpb = (T / kWave) * Geo<R>::GPW;
-  int blocks = grid_for(n, gpb * 16);
-  hipLaunchKernelGGL(k_gram_tall<R>, dim3(blocks), dim3(T), sizeof(double) * R * R, s, A, n, lda,
-                     out);
+hipError_t gram_t(const BatchView& b, int which, int parity, hipStream_t s) {
+  const int gpb = (256 / kWave) * Geo<R>::GPW;
+  const int gx = grid_for(which == 0 ? b.maxK : b.maxJ, gpb * 16);
+  hipLaunchKernelGGL(k_gram<R>, dim3(gx, b.np), dim3(256), sizeof(double) * R * R, s, b.desc,
+                     which, parity);
   return hipGetLastError();
 }
 
@@ -1218,39 +1417,6 @@ int mode2_max_hot(int R) {
   }
 }
 
-hipError_t run_alpha(int R, const XEnc& X, int64_t K, const float* V, const float* W,
-                     const double* H, float* F, double* M1, const PolarParams& pp,
-                     hipStream_t s) {
-  P2_DISPATCH(R, return alpha_t<RR>(X, K, V, W, H, F, M1, pp, s))
-}
-
-hipError_t run_gamma(int R, const XEnc& X, int64_t K, const float* V0, const float* V1, float* W,
-                     const double* H, const double* N3, const double* N3p, float* F, float* M3,
-                     double* M1next, double* fitacc, int do_next, const PolarParams& pp,
-                     hipStream_t s) {
-  P2_DISPATCH(R, return gamma_t<RR>(X, K, V0, V1, W, H, N3, N3p, F, M3, M1next, fitacc, do_next,
-                                    pp, s))
-}
-
-hipError_t run_mode2(int R, const XEnc& X, int64_t K, const float* V, const float* W,
-                     const double* H, const float* F, float* M2, float* part, int hot,
-                     hipStream_t s) {
-  P2_DISPATCH(R, return mode2_t<RR>(X, K, V, W, H, F, M2, part, hot, s))
-}
-
-size_t mode2_part_bytes(int R, int64_t K, int hot) {
-  if (hot <= 0) return 0;
-  switch (R) {
-#define P2_CASE(r) \
-  case r:          \
-    return sizeof(float) * (size_t)mode2_blocks_t<r>(K) * (size_t)hot * r;
-    P2_RANKS(P2_CASE)
-#undef P2_CASE
-    default:
-      return 0;
-  }
-}
-
 size_t launch_lds(int R, int kernel) {
   switch (R) {
 #define P2_CASE(r)                                                                          \
@@ -1287,38 +1453,6 @@ int launch_threads(int R, int kernel) {
     default:
       return 0;
   }
-}
-
-hipError_t run_gram_tall(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s) {
-  P2_DISPATCH(R, return gram_tall_t<RR>(A, n, lda, out, s))
-}
-
-hipError_t run_solve_h(int R, const double* M1, const double* WtW, const double* VtV, double* H,
-                       double* HtH, double* N2p, const PolarParams& pp, hipStream_t s) {
-  P2_DISPATCH(R, hipLaunchKernelGGL(k_solve_h<RR>, dim3(1), dim3(64), 0, s, M1, WtW, VtV, H, HtH,
-                                    N2p, pp);
-              return hipGetLastError())
-}
-
-hipError_t run_vupdate(int R, const float* M2, const double* N2p, int64_t J, float* Vout,
-                       hipStream_t s) {
-  P2_DISPATCH(R, hipLaunchKernelGGL(k_vupdate<RR>, dim3(grid1(J)), dim3(256), 0, s, M2, N2p, J,
-                                    Vout);
-              return hipGetLastError())
-}
-
-hipError_t run_solve_n3(int R, const double* VtVraw, const double* HtH, double* VtV,
-                        double* invnorm, double* N3, double* N3p, const PolarParams& pp,
-                        hipStream_t s) {
-  P2_DISPATCH(R, hipLaunchKernelGGL(k_solve_n3<RR>, dim3(1), dim3(64), 0, s, VtVraw, HtH, VtV,
-                                    invnorm, N3, N3p, pp);
-              return hipGetLastError())
-}
-
-hipError_t run_vscale(int R, float* V, int64_t J, const double* invnorm, hipStream_t s) {
-  P2_DISPATCH(R, hipLaunchKernelGGL(k_vscale<RR>, dim3(grid1(J * Geo<RR>::LDV)), dim3(256), 0, s,
-                                    V, J, invnorm);
-              return hipGetLastError())
 }
 
 hipError_t run_getq(int R, const XEnc& X, int64_t k0, int64_t k1, const float* V, const float* F,
@@ -1395,9 +1529,93 @@ hipError_t run_iota(int32_t* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t run_fit(const double* fitacc, const double* nx2, double* fit_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit, dim3(1), dim3(64), 0, s, fitacc, nx2, fit_out);
+int polar_tile_unit(int R) {
+  switch (R) {
+#define P2_CASE(r) \
+  case r:          \
+    return polar_gpb<r>();
+    P2_RANKS(P2_CASE)
+#undef P2_CASE
+    default:
+      return 0;
+  }
+}
+
+int mode2_tile_unit(int R) {
+  switch (R) {
+#define P2_CASE(r) \
+  case r:          \
+    return mode2_gpb<r>();
+    P2_RANKS(P2_CASE)
+#undef P2_CASE
+    default:
+      return 0;
+  }
+}
+
+hipError_t plan_launch(BatchView& b) { P2_DISPATCH(b.R, return plan_t<RR>(b)) }
+
+hipError_t run_alpha(const BatchView& b, int parity, const PolarParams& pp, hipStream_t s) {
+  P2_DISPATCH(b.R, return alpha_t<RR>(b, parity, pp, s))
+}
+
+hipError_t run_gamma(const BatchView& b, int parity, int do_next, const PolarParams& pp,
+                     hipStream_t s) {
+  P2_DISPATCH(b.R, return gamma_t<RR>(b, parity, do_next, pp, s))
+}
+
+hipError_t run_mode2(const BatchView& b, int parity, hipStream_t s) {
+  P2_DISPATCH(b.R, return mode2_t<RR>(b, parity, s))
+}
+
+hipError_t run_gram(const BatchView& b, int which, int parity, hipStream_t s) {
+  P2_DISPATCH(b.R, return gram_t<RR>(b, which, parity, s))
+}
+
+hipError_t run_solve_h(const BatchView& b, const PolarParams& pp, hipStream_t s) {
+  P2_DISPATCH(b.R, hipLaunchKernelGGL(k_solve_h<RR>, dim3(b.np), dim3(64), 0, s, b.desc, pp);
+              return hipGetLastError())
+}
+
+hipError_t run_vupdate(const BatchView& b, int parity, hipStream_t s) {
+  P2_DISPATCH(b.R, hipLaunchKernelGGL(k_vupdate<RR>, dim3(grid1(b.maxJ), b.np), dim3(256), 0, s,
+                                      b.desc, parity);
+              return hipGetLastError())
+}
+
+hipError_t run_solve_n3(const BatchView& b, const PolarParams& pp, hipStream_t s) {
+  P2_DISPATCH(b.R, hipLaunchKernelGGL(k_solve_n3<RR>, dim3(b.np), dim3(64), 0, s, b.desc, pp);
+              return hipGetLastError())
+}
+
+hipError_t run_vscale(const BatchView& b, int parity, hipStream_t s) {
+  P2_DISPATCH(b.R, hipLaunchKernelGGL(k_vscale<RR>, dim3(grid1(b.maxJ * Geo<RR>::LDV), b.np),
+                                      dim3(256), 0, s, b.desc, parity);
+              return hipGetLastError())
+}
+
+hipError_t run_zero(const BatchView& b, int mask, hipStream_t s) {
+  const int gx = (mask & 16) ? grid1(b.maxJ * ((b.R + 3) & ~3)) : 1;
+  P2_DISPATCH(b.R, hipLaunchKernelGGL(k_zero<RR>, dim3(gx, b.np), dim3(256), 0, s, b.desc, mask);
+              return hipGetLastError())
+}
+
+hipError_t run_fit(const BatchView& b, hipStream_t s) {
+  P2_DISPATCH(b.R, hipLaunchKernelGGL(k_fit<RR>, dim3(b.np), dim3(64), 0, s, b.desc);
+              return hipGetLastError())
+}
+
+hipError_t run_reset_tickets(const BatchView& b, hipStream_t s) {
+  if (!b.dynamic) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, b.tickets, kTicketKinds * kBins, 0);
   return hipGetLastError();
+}
+
+hipError_t run_gram_rows(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s) {
+  P2_DISPATCH(R, const int gpb = (256 / kWave) * Geo<RR>::GPW;
+              hipLaunchKernelGGL(k_gram_rows<RR>, dim3(grid_for(n, gpb * 16)), dim3(256),
+                                 sizeof(double) * RR * RR, s, A, n, lda, out);
+              return hipGetLastError())
 }
 
 }  // namespace p2

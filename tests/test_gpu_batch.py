@@ -1,0 +1,154 @@
+"""GPU: batches of independent problems, launch schedules and graph replay.
+
+Every schedule and the batched launch compute the same iteration; results
+differ only in the order of floating-point atomic additions, and ALS carries
+such differences on, amplified on ill-conditioned subjects.  Tolerances:
+  * after one iteration from the same state: factors within 1e-5 relative;
+  * over several iterations: fits within 1e-6, factors within 1e-4 relative
+    (the batched-vs-single bar);
+  * a batch member against the FP64 oracle: the single-problem bar (MTTKRPs
+    and factors 1e-4 relative, fit 1e-5).
+"""
+import numpy as np
+import pytest
+
+from datagen import gen_config, gen_init
+from datagen.synth import gen_batched_problem, gen_batched_specs
+from oracle import parafac2_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1703_04219_amd import binding as B  # noqa: E402
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _problems(n=6, k_scale=0.04):
+    specs = gen_batched_specs(n, k_scale=k_scale)
+    out = []
+    for i, sp in enumerate(specs):
+        X = gen_batched_problem(sp)
+        H0, V0, W0 = gen_init(X.J, X.K, sp["R"], [170304219, 4, 7, i])
+        out.append((X, sp["R"], H0, V0, W0))
+    return out
+
+
+def _ctx(X, R, H0, V0, W0, **sched):
+    opts = B.make_opts(sched=B.make_sched(**sched)) if sched else None
+    return B.Context(B.DeviceSlices.from_slices(X), R, H0, V0, W0, opts)
+
+
+def _state(ctx):
+    return (ctx.H.cpu().numpy().copy(), ctx.V.cpu().numpy().copy(), ctx.W.cpu().numpy().copy())
+
+
+def test_batch_member_matches_oracle():
+    probs = _problems()
+    ctxs = [_ctx(*p) for p in probs]
+    batch = B.Batch(ctxs)
+    fits = batch.iterate(1)
+    torch.cuda.synchronize()
+    print("ranks", [p[1] for p in probs], "K", [p[0].K for p in probs], flush=True)
+    for b in (0, len(probs) - 1):
+        X, R, H0, V0, W0 = probs[b]
+        Xs = O.slices_to_list(X.subj_ptr, X.row_ptr, X.col, X.val, X.J)
+        H1, V1, W1, info = O.iterate(Xs, H0, V0, W0, dense_loss=False)
+        M1, M2, M3 = (t.cpu().numpy() for t in ctxs[b].mttkrp())
+        H, V, W = _state(ctxs[b])
+        errs = dict(M1=rel(M1, info["M1"]), M2=rel(M2, info["M2"]), M3=rel(M3, info["M3"]),
+                    H=rel(H, H1), V=rel(V, V1), W=rel(W, W1), fit=abs(fits[0, b] - info["fit"]))
+        print(f"member {b} R={R} K={X.K}:", ", ".join(f"{k}={v:.2e}" for k, v in errs.items()),
+              flush=True)
+        for k in ("M1", "M2", "M3", "H", "V", "W"):
+            assert errs[k] <= 1e-4, (b, k, errs[k])
+        assert errs["fit"] <= 1e-5
+
+
+@pytest.mark.parametrize("sched", [dict(), dict(dynamic=1, tile_rounds=1, m2_tiles=16, graph=1)])
+def test_batch_equals_one_problem_at_a_time(sched):
+    probs = _problems()
+    single = [_ctx(*p) for p in probs]
+    fs = np.stack([c.iterate(4) for c in single], axis=1)
+    batched = [_ctx(*p) for p in probs]
+    batch = B.Batch(batched, B.make_sched(**sched) if sched else None)
+    fb = batch.iterate(4)
+    torch.cuda.synchronize()
+    print("max fit diff", np.abs(fb - fs).max(), flush=True)
+    assert np.abs(fb - fs).max() <= 1e-6
+    for a, b in zip(single, batched):
+        for x, y in zip(_state(b), _state(a)):
+            assert rel(x, y) <= 1e-4
+
+
+@pytest.mark.parametrize("sched", [
+    dict(tile_rounds=1), dict(tile_rounds=16), dict(dynamic=1), dict(dynamic=1, tile_rounds=2),
+    dict(m2_tiles=8), dict(graph=1), dict(graph=1, dynamic=1)])
+def test_schedules_agree(sched):
+    X, R = gen_config(2, k_limit=6000)
+    H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, 2, 1])
+    ref = _ctx(X, R, H0, V0, W0)
+    alt = _ctx(X, R, H0, V0, W0, **sched)
+    fr, fa = [ref.iterate(1)], [alt.iterate(1)]
+    torch.cuda.synchronize()
+    one = [rel(x, y) for x, y in zip(_state(alt), _state(ref))]
+    fr.append(ref.iterate(2))
+    fa.append(alt.iterate(2))
+    torch.cuda.synchronize()
+    fr, fa = np.concatenate(fr), np.concatenate(fa)
+    three = [rel(x, y) for x, y in zip(_state(alt), _state(ref))]
+    print(sched, "fit diff", np.abs(fa - fr).max(), "H/V/W after 1:", one, "after 3:", three,
+          flush=True)
+    assert max(one) <= 1e-5
+    assert np.abs(fa - fr).max() <= 1e-6
+    assert max(three) <= 1e-4
+
+
+def test_graph_replays_match_plain_launches():
+    # graphs are replayed many times with other device work and host
+    # synchronisation in between; every replay must match the plain path
+    X, R = gen_config(1)
+    H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, 1, 1])
+    plain = _ctx(X, R, H0, V0, W0)
+    graph = _ctx(X, R, H0, V0, W0, graph=1)
+    fp, fg = [], []
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for rep in range(4):
+        fp.append(plain.iterate(3))
+        scratch.add_(1.0)
+        torch.cuda.synchronize()
+        fg.append(graph.iterate(3))
+        scratch.mul_(0.5)
+        torch.cuda.synchronize()
+    fp, fg = np.concatenate(fp), np.concatenate(fg)
+    print("graph vs plain fits", np.abs(fg - fp).max(), flush=True)
+    assert np.abs(fg - fp).max() <= 1e-6
+    for x, y in zip(_state(graph), _state(plain)):
+        assert rel(x, y) <= 1e-4
+
+
+def test_autotune_keeps_the_iteration():
+    probs = _problems(4)
+    ctxs = [_ctx(*p) for p in probs]
+    batch = B.Batch(ctxs)
+    sc, ms = batch.autotune(1)
+    print("chosen", sc.as_dict(), f"{ms:.3f} ms/iteration", flush=True)
+    assert sc.tile_rounds in (1, 2, 4, 8, 16) and sc.dynamic in (0, 1) and ms > 0
+    f = batch.iterate(5)
+    assert np.all(np.diff(f, axis=0) >= -1e-6)
+
+
+def test_batch_refuses_contexts_out_of_step():
+    probs = _problems(2)
+    a, b = _ctx(*probs[0]), _ctx(*probs[1])
+    a.iterate(1)
+    with pytest.raises(B.Parafac2Error) as e:
+        B.Batch([a, b]).iterate(1)
+    assert e.value.code == B.P2_ESTATE
