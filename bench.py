@@ -32,12 +32,17 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    p.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                   help="1-3 one decomposition; 4 the 64-problem batch; 5 the serving trace")
     p.add_argument("--k-limit", type=int, default=None, help="only the first K subjects")
     p.add_argument("--cpu-subjects", type=int, default=30000,
                    help="subjects in the oracle's timed sample (0 = skip)")
     p.add_argument("--profile-only", action="store_true",
                    help="skip the CPU baseline (for profiler runs)")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the default launch schedule instead of autotuning it")
+    p.add_argument("--serve-seconds", type=float, default=10.0,
+                   help="measured seconds of the serving trace (after 1 s of warm-up)")
     p.add_argument("--copy-bytes", type=int, default=0,
                    help="only run a plain device-to-device copy of this many bytes (calibrates "
                         "the profiler's FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -83,6 +88,165 @@ def cpu_baseline(cfg: int, n_subjects: int):
                       f"FP64 NumPy/LAPACK, one thread, {dt:.1f} s"}
 
 
+def _request(X, k):
+    r0, r1 = int(X.subj_ptr[k]), int(X.subj_ptr[k + 1])
+    rp = X.row_ptr[r0:r1 + 1]
+    z0, z1 = int(rp[0]), int(rp[-1])
+    return (np.ascontiguousarray(rp - rp[0]), np.ascontiguousarray(X.col[z0:z1]),
+            np.ascontiguousarray(X.val[z0:z1]))
+
+
+def replay(server, t, reqs, stop_after: float):
+    """Replay arrival times t (seconds) against the server in real time;
+    returns each request's completion time (nan if not done by stop_after)."""
+    n = len(t)
+    done = np.full(n, np.nan)
+    i, ndone = 0, 0
+    t0 = time.perf_counter()
+    while ndone < n:
+        now = time.perf_counter() - t0
+        if now > stop_after:
+            break
+        while i < n and t[i] <= now:
+            if server.submit(i, *reqs[i]) != 0:
+                break  # queue full: the request waits on the client side
+            i += 1
+        ids, _, _ = server.poll()
+        if len(ids):
+            done[ids] = time.perf_counter() - t0
+            ndone += len(ids)
+    return done
+
+
+def serving(a) -> dict:
+    import torch
+
+    from datagen.synth import gen_serving_model, gen_serving_requests
+    from paper_1703_04219_amd import binding as B
+    warm, dur, rate = 1.0, a.serve_seconds, 2000.0
+    V, H = gen_serving_model()
+    t, X = gen_serving_requests(int((warm + dur) * rate))
+    reqs = [_request(X, k) for k in range(X.K)]
+    nnz_req = X.nnz / X.K
+    torch.cuda.set_device(0)
+    model = B.Model(V, H)
+    out = {}
+    for name, kw in (("continuous", dict(slots=4, max_requests=512)),
+                     ("one_at_a_time", dict(slots=1, max_requests=1))):
+        server = B.Server(model, **kw)
+        for k in range(64):  # warm the kernels and the staging buffers
+            server.submit(k, *reqs[k])
+        server.drain()
+        server.poll()
+        # idle latency: one request at a time on an empty server
+        idle = []
+        for k in range(20):
+            t1 = time.perf_counter()
+            server.submit(k, *reqs[k])
+            server.drain()
+            server.poll()
+            idle.append((time.perf_counter() - t1) * 1e3)
+        # saturation: a backlog of 1000 requests (500 for the plain path) drained
+        nb = 1000 if kw["max_requests"] > 1 else 200
+        t1 = time.perf_counter()
+        for k in range(nb):
+            server.submit(k, *reqs[k])
+        server.drain()
+        server.poll()
+        sat = nb / (time.perf_counter() - t1)
+        # the Poisson trace: 1 s of warm-up arrivals, then the measured window
+        span = dur if kw["max_requests"] > 1 else min(dur, 2.0)
+        m = int(np.searchsorted(t, warm + span))
+        done = replay(server, t[:m], reqs[:m], stop_after=warm + span + 5.0)
+        server.drain()
+        lat = done - t[:m]
+        sel = t[:m] >= warm
+        ok = np.isfinite(lat) & sel
+        lat_ms = lat[ok] * 1e3
+        span_s = float(np.nanmax(done[sel]) - warm) if ok.any() else float("nan")
+        out[name] = {"p50_ms": float(np.percentile(lat_ms, 50)) if ok.any() else None,
+                     "p99_ms": float(np.percentile(lat_ms, 99)) if ok.any() else None,
+                     "completed": int(ok.sum()), "offered": int(sel.sum()),
+                     "throughput_req_s": float(ok.sum() / span_s) if ok.any() else 0.0,
+                     "measured_s": span,
+                     "idle_latency_ms_p50": float(np.median(idle)),
+                     "saturation_req_s": float(sat), "server": kw}
+        print(f"[bench] serving {name}: {out[name]}", file=sys.stderr, flush=True)
+        server.close()
+    out["rate_req_s"] = rate
+    out["nnz_per_request"] = round(nnz_req, 1)
+    out["R"] = int(V.shape[1])
+    return out
+
+
+def batched(a):
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    from datagen.synth import gen_batched_problem, gen_batched_specs
+    from datagen import gen_init
+    specs = gen_batched_specs()
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
+                                mp_context=mp.get_context("fork")) as ex:
+        Xs = list(ex.map(gen_batched_problem, specs))
+    nnz = sum(X.nnz for X in Xs)
+    print(f"[bench] generated 64 problems, {nnz} nnz, in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    import torch
+
+    from paper_1703_04219_amd import binding as B
+    torch.cuda.set_device(0)
+    ctxs = []
+    for i, (sp, X) in enumerate(zip(specs, Xs)):
+        H0, V0, W0 = gen_init(X.J, X.K, sp["R"], [170304219, 4, 1, i])
+        ctxs.append(B.Context(B.DeviceSlices.from_slices(X), sp["R"], H0, V0, W0))
+    del Xs
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # one problem at a time (each context runs its own launches)
+    for c in ctxs:
+        c.iterate(a.warmup, with_fit=False)
+    torch.cuda.synchronize()
+    e0.record()
+    for c in ctxs:
+        c.iterate(a.steps, with_fit=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1) / a.steps
+    # the batch: one launch per rank class and kernel, autotuned schedule
+    batch = B.Batch(ctxs, B.make_sched(graph=1))
+    chosen, tuned_ms = (None, None) if a.no_autotune else batch.autotune(2)
+    batch.iterate(a.warmup, with_fit=False)
+    torch.cuda.synchronize()
+    e0.record()
+    batch.iterate(a.steps, with_fit=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / a.steps
+    fits = batch.iterate(1)[0]
+    print(f"[bench] batched {ms_batch:.3f} ms/iteration vs one problem at a time "
+          f"{ms_single:.3f} ms; schedule {chosen.as_dict() if chosen else 'default'}",
+          file=sys.stderr, flush=True)
+    out = {
+        "metric": "ALS-iteration nnz/s & % HBM roofline at R=10/40; p50/p99 projection latency",
+        "value": nnz / (ms_batch * 1e-3), "unit": "nnz/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 sparse products, f64 RxR", "data": "synthetic",
+        "config": {"workload": "c4_batched_64_problems", "problems": len(ctxs), "nnz": nnz,
+                   "K_total": int(sum(c.X.K for c in ctxs)),
+                   "ranks": {str(r): sum(1 for sp in specs if sp["R"] == r) for r in (5, 10, 20)},
+                   "one_problem_at_a_time_ms": ms_single,
+                   "one_problem_at_a_time_nnz_s": nnz / (ms_single * 1e-3),
+                   "speedup_vs_one_at_a_time": ms_single / ms_batch,
+                   "schedule": chosen.as_dict() if chosen else None,
+                   "autotune_ms_per_iteration": tuned_ms,
+                   "min_fit_after": float(np.min(fits))},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_bytes:
@@ -92,6 +256,20 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
               "subject-sharded design is described but not built.", file=sys.stderr)
         sys.exit(2)
+    if a.config == 4:
+        batched(a)
+        return
+    if a.config == 5:
+        res = serving(a)
+        c = res["continuous"]
+        print(json.dumps({
+            "metric": "ALS-iteration nnz/s & % HBM roofline at R=10/40; p50/p99 projection latency",
+            "value": c["p99_ms"], "unit": "ms (p99 latency)", "n_gpus": 1, "steps": c["completed"],
+            "warmup": 1, "ms_per_step": c["p50_ms"], "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32 gather, f64 RxR",
+            "data": "synthetic", "config": {"workload": "c5_serving_2000req_s", **res},
+            "roofline": None, "cpu_baseline": None}), flush=True)
+        return
     import torch
 
     from datagen import CONFIGS, gen_config, gen_init
@@ -109,6 +287,11 @@ def main():
     del dX  # the context re-encoded the input into its workspace
     torch.cuda.synchronize()
     print(f"[bench] init done, workspace {ctx.ws_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+    chosen, tuned_ms = None, None
+    if not a.no_autotune:
+        chosen, tuned_ms = ctx.autotune(2)
+        print(f"[bench] autotuned schedule {chosen.as_dict()} ({tuned_ms:.3f} ms/iteration)",
+              file=sys.stderr, flush=True)
     if a.warmup:
         ctx.iterate(a.warmup, with_fit=False)
     torch.cuda.synchronize()
@@ -178,6 +361,7 @@ def main():
         "config": {"workload": name, "K": X.K, "J": X.J, "R": R, "n_rows": X.n_rows,
                    "nnz": X.nnz, "fit_after": fit,
                    "phase_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
+                   "schedule": chosen.as_dict() if chosen else None,
                    "paper_context": "SPARTan: 7.4 min/iteration at 63M nnz, R=10 (4x Xeon E5-4620 v4, "
                                     "NNLS-constrained, uniform sparsity)"},
         "roofline": roof,

@@ -45,7 +45,8 @@ enum {
   P2_ENOMEM = -2,  /* workspace smaller than parafac2_workspace_size() asked for */
   P2_EDEVICE = -3, /* a HIP call failed; the context is then unusable           */
   P2_ESTATE = -4,  /* context or model is in a failed state                    */
-  P2_ENOTSUP = -5  /* valid input outside what this build supports (e.g. R)    */
+  P2_ENOTSUP = -5, /* valid input outside what this build supports (e.g. R)    */
+  P2_EBUSY = -6    /* a server's request queue is full; poll and submit again   */
 };
 
 #define PARAFAC2_ABI_VERSION 1
@@ -284,6 +285,69 @@ int parafac2_project(parafac2_model* m, const parafac2_csr* req, int32_t n_steps
                      float* Q_out, float* w_out, double* loss_out, void* stream);
 
 void parafac2_model_destroy(parafac2_model* m);
+
+/* ---- serving: continuous batching of projection requests ------------------
+ * A server projects requests (single new subjects, each an I x J slice in
+ * host memory) onto a model as they arrive.  Requests wait in a bounded host
+ * queue; whenever one of the server's batch slots is free, the queued
+ * requests at the front that fit the slot's capacity (requests, rows,
+ * nonzeros: the slot's share of the workspace) are packed into it, copied to
+ * the device and projected on the slot's own stream, so batches run and copy
+ * while others are in flight.  Every request is computed exactly as by
+ * parafac2_project on its own (same kernel, results depend only on its own
+ * slice), so a result is bitwise the same alone and in any mix.
+ * The server allocates pinned host staging buffers and one stream per slot
+ * (default priority) at create time; device memory comes from the workspace.
+ * Not thread-safe: one thread submits and polls. */
+typedef struct parafac2_server parafac2_server;
+
+typedef struct {
+  int32_t slots;        /* batches in flight; 0 -> 4                        */
+  int32_t max_requests; /* requests per batch; 0 -> 512                     */
+  int64_t max_rows;     /* rows per batch; 0 -> 65536                       */
+  int64_t max_nnz;      /* nonzeros per batch; 0 -> 1 << 21                 */
+  int32_t max_queue;    /* requests waiting on the host; 0 -> 1 << 16       */
+  int32_t n_steps;      /* alternations per request; 0 -> 10                */
+  int32_t want_q;       /* 1: also return each request's Q (I x R)          */
+  int32_t reserved[5];
+} parafac2_server_opts;
+
+/* Device workspace bytes of a server over model m. */
+int parafac2_server_workspace_size(const parafac2_model* m, const parafac2_server_opts* o,
+                                   size_t* bytes);
+
+/* Create a server (workspace: device, 256-byte aligned, borrowed until
+ * destroy; the model must outlive the server). */
+int parafac2_server_create(parafac2_server** out, parafac2_model* m,
+                           const parafac2_server_opts* o, void* workspace, size_t ws_bytes);
+
+/* Queue one request, copied from host memory: I rows, row_ptr (host, I+1
+ * offsets from 0), col (host, nnz, in [0, J)), val (host, nnz, finite).
+ * P2_EINVAL if the request is malformed, has I < R, or can never fit one
+ * batch; P2_EBUSY if the queue is full.  Launches nothing by itself. */
+int parafac2_server_submit(parafac2_server* s, int64_t id, int32_t I, const int64_t* row_ptr,
+                           const int32_t* col, const float* val);
+
+/* Collect finished batches and start queued requests on free slots, then
+ * return up to max_out finished results in completion order: ids (host,
+ * max_out), w (host, max_out x R float32), loss (host, max_out float64,
+ * ||X - Q H diag(w) V^T||_F^2, or NULL); with want_q, q (host, q_cap rows x R
+ * float32, concatenated in result order) and q_rows (host, max_out) -- a
+ * result whose Q no longer fits q_cap stays for the next poll.  *n_out gets
+ * the number returned.  Never blocks. */
+int parafac2_server_poll(parafac2_server* s, int32_t max_out, int64_t* ids, float* w,
+                         double* loss, float* q, int64_t q_cap, int32_t* q_rows, int32_t* n_out);
+
+/* Requests queued on the host, in flight on the device, and finished but not
+ * yet returned by poll. */
+int parafac2_server_pending(parafac2_server* s, int64_t* queued, int64_t* in_flight,
+                            int64_t* finished);
+
+/* Wait for every request in flight to finish (queued ones are started as
+ * slots free up), without returning results. */
+int parafac2_server_drain(parafac2_server* s);
+
+void parafac2_server_destroy(parafac2_server* s);
 
 #ifdef __cplusplus
 }

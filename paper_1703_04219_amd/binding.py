@@ -17,9 +17,9 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libparafac2.so")
 
-P2_OK, P2_EINVAL, P2_ENOMEM, P2_EDEVICE, P2_ESTATE, P2_ENOTSUP = 0, -1, -2, -3, -4, -5
+P2_OK, P2_EINVAL, P2_ENOMEM, P2_EDEVICE, P2_ESTATE, P2_ENOTSUP, P2_EBUSY = 0, -1, -2, -3, -4, -5, -6
 _STATUS = {P2_EINVAL: "EINVAL", P2_ENOMEM: "ENOMEM", P2_EDEVICE: "EDEVICE",
-           P2_ESTATE: "ESTATE", P2_ENOTSUP: "ENOTSUP"}
+           P2_ESTATE: "ESTATE", P2_ENOTSUP: "ENOTSUP", P2_EBUSY: "EBUSY"}
 
 SUPPORTED_R = (1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 32, 40)
 
@@ -50,6 +50,13 @@ class Opts(ctypes.Structure):
                 ("hot_cols", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("sched", Sched), ("m2_capacity", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 3)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_requests", ctypes.c_int32),
+                ("max_rows", ctypes.c_int64), ("max_nnz", ctypes.c_int64),
+                ("max_queue", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("want_q", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 _lib = None
@@ -92,6 +99,13 @@ def load(path: str = LIB_PATH):
         "parafac2_batch_set_profiling": (ctypes.c_int, [vp, i32]),
         "parafac2_batch_get_profile": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int64)]),
         "parafac2_batch_destroy": (None, [vp]),
+        "parafac2_server_workspace_size": (ctypes.c_int, [vp, P(ServerOpts), P(sz)]),
+        "parafac2_server_create": (ctypes.c_int, [P(vp), vp, P(ServerOpts), vp, sz]),
+        "parafac2_server_submit": (ctypes.c_int, [vp, i64, i32, vp, vp, vp]),
+        "parafac2_server_poll": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, i64, vp, P(i32)]),
+        "parafac2_server_pending": (ctypes.c_int, [vp, P(i64), P(i64), P(i64)]),
+        "parafac2_server_drain": (ctypes.c_int, [vp]),
+        "parafac2_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -110,7 +124,10 @@ def exported_symbols() -> list:
             "parafac2_model_destroy", "parafac2_set_sched", "parafac2_autotune",
             "parafac2_batch_workspace_size", "parafac2_batch_create", "parafac2_batch_iterate",
             "parafac2_batch_set_sched", "parafac2_batch_autotune", "parafac2_batch_set_profiling",
-            "parafac2_batch_get_profile", "parafac2_batch_destroy"]
+            "parafac2_batch_get_profile", "parafac2_batch_destroy",
+            "parafac2_server_workspace_size", "parafac2_server_create", "parafac2_server_submit",
+            "parafac2_server_poll", "parafac2_server_pending", "parafac2_server_drain",
+            "parafac2_server_destroy"]
 
 
 def _check(rc: int):
@@ -413,6 +430,85 @@ class Model:
             pass
 
 
+class Server:
+    """Continuous-batching projection server over a Model (parafac2_server_*)."""
+
+    def __init__(self, model: Model, slots=0, max_requests=0, max_rows=0, max_nnz=0,
+                 max_queue=0, n_steps=0, want_q=False, poll_cap=4096):
+        self.lib = load()
+        self.model = model  # the model must outlive the server
+        self.R = model.R
+        self.opts = ServerOpts(slots, max_requests, max_rows, max_nnz, max_queue, n_steps,
+                               1 if want_q else 0)
+        nb = ctypes.c_size_t(0)
+        _check(self.lib.parafac2_server_workspace_size(model.handle, ctypes.byref(self.opts),
+                                                       ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self._ws, wsp = _workspace(self.ws_bytes, model.V.device)
+        h = ctypes.c_void_p(0)
+        _check(self.lib.parafac2_server_create(ctypes.byref(h), model.handle,
+                                               ctypes.byref(self.opts), wsp, self.ws_bytes))
+        self.handle = h
+        self.want_q = bool(want_q)
+        self._cap = int(poll_cap)
+        self._ids = np.zeros(self._cap, np.int64)
+        self._w = np.zeros((self._cap, self.R), np.float32)
+        self._loss = np.zeros(self._cap, np.float64)
+        self._qrows = np.zeros(self._cap, np.int32)
+        self._qcap = self._cap * 128 if want_q else 0
+        self._q = np.zeros((max(self._qcap, 1), self.R), np.float32)
+        self._n = ctypes.c_int32(0)
+
+    def submit(self, rid: int, row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray) -> int:
+        """Queue a request (host arrays, row_ptr from 0); returns the status
+        (P2_OK or P2_EBUSY; other errors raise)."""
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float32)
+        rc = self.lib.parafac2_server_submit(self.handle, int(rid), int(row_ptr.shape[0] - 1),
+                                             row_ptr.ctypes.data, col.ctypes.data,
+                                             val.ctypes.data)
+        if rc not in (P2_OK, P2_EBUSY):
+            _check(rc)
+        return rc
+
+    def poll(self):
+        """(ids, w, loss[, q list]) of the requests finished since the last poll."""
+        _check(self.lib.parafac2_server_poll(
+            self.handle, self._cap, self._ids.ctypes.data, self._w.ctypes.data,
+            self._loss.ctypes.data, self._q.ctypes.data if self.want_q else None, self._qcap,
+            self._qrows.ctypes.data if self.want_q else None, ctypes.byref(self._n)))
+        n = self._n.value
+        out = (self._ids[:n].copy(), self._w[:n].copy(), self._loss[:n].copy())
+        if self.want_q:
+            qs, r0 = [], 0
+            for r in self._qrows[:n]:
+                qs.append(self._q[r0:r0 + r].copy())
+                r0 += int(r)
+            out = out + (qs,)
+        return out
+
+    def pending(self) -> tuple:
+        a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(self.lib.parafac2_server_pending(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                                ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def drain(self):
+        _check(self.lib.parafac2_server_drain(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.parafac2_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # C-ABI names at module level -------------------------------------------------
 
 def parafac2_init(X: DeviceSlices, R: int, H, V, W, opts: Optional[Opts] = None,
@@ -454,6 +550,10 @@ def parafac2_batch_autotune(batch: Batch, iters_per_trial: int = 2):
 
 def parafac2_model_create(V, H, stream=None) -> Model:
     return Model(V, H, stream)
+
+
+def parafac2_server_create(model: Model, **opts) -> Server:
+    return Server(model, **opts)
 
 
 def parafac2_project(model: Model, X: DeviceSlices, n_steps: int = 10, w0=None,

@@ -27,14 +27,15 @@
 #include "../../include/parafac2.h"
 #include "p2_batch.h"
 #include "p2_device.h"
+#include "p2_host.h"
 #include "p2_kernels.h"
 
-namespace {
+namespace p2host {
 
-using p2::kBins;
-using p2::kFitRing;
-
-thread_local std::string g_last_error;
+std::string& last_error() {
+  static thread_local std::string s;
+  return s;
+}
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -42,9 +43,18 @@ int fail(int code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof(buf), fmt, ap);
   va_end(ap);
-  g_last_error = buf;
+  last_error() = buf;
   return code;
 }
+
+}  // namespace p2host
+
+namespace {
+
+using p2::kBins;
+using p2::kFitRing;
+
+using p2host::fail;
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -678,15 +688,6 @@ struct parafac2_batch {
   ~parafac2_batch() { delete r; }
 };
 
-struct parafac2_model {
-  int64_t J = 0;
-  int R = 0, LDV = 0;
-  hipStream_t stream = nullptr;
-  unsigned char* ws = nullptr;
-  size_t oV = 0, oH = 0, oN3 = 0, oN3p = 0, oVtV = 0, oHtH = 0, oMap = 0, total = 0;
-  p2::PolarParams pp{};
-};
-
 // ---------------------------------------------------------------------------
 // host-side validation
 // ---------------------------------------------------------------------------
@@ -763,7 +764,7 @@ extern "C" {
 
 int parafac2_abi_version(void) { return PARAFAC2_ABI_VERSION; }
 
-const char* parafac2_last_error(void) { return g_last_error.c_str(); }
+const char* parafac2_last_error(void) { return p2host::last_error().c_str(); }
 
 int parafac2_validate_host(const parafac2_csr* host_X, int32_t R, char* msg, size_t msg_len) {
   std::string m;
@@ -772,7 +773,7 @@ int parafac2_validate_host(const parafac2_csr* host_X, int32_t R, char* msg, siz
     std::strncpy(msg, m.c_str(), msg_len - 1);
     msg[msg_len - 1] = 0;
   }
-  if (rc != P2_OK) g_last_error = m;
+  if (rc != P2_OK) p2host::last_error() = m;
   return rc;
 }
 
@@ -907,7 +908,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
     if (rp != P2_OK) return cleanup(rp);
   }
   *out = c;
-  g_last_error.clear();
+  p2host::last_error().clear();
   return P2_OK;
 #undef INIT_TRY
 }
