@@ -482,14 +482,19 @@ __device__ __forceinline__ void factor_c(const double* Cs, double* Ec, double* s
 
 // One factored Procrustes step.  On exit lane c (< R) holds (Y V)(:, c) in yv
 // and, if want_f, row c of F in fr.  S and S2 are group LDS scratch of
-// NC x R doubles each, dl of NC doubles.
+// NC x R doubles each, dl of NC doubles.  vb is lane c's column of an
+// orthonormal start basis for the right singular vectors (e_c for a cold
+// start); on exit it holds this step's right singular vector at position c,
+// so that a following step with a nearby w (warm) starts from T V_prev,
+// whose columns are already nearly orthogonal, and needs fewer sweeps.
 template <int R>
 __device__ __forceinline__ void polar_factored(const double* Ec, const double* sv,
                                                const double* isv, const double* w,
                                                const double* Hs, double* S, double* S2,
                                                double* dl, int c, int gbase, uint64_t gmask,
                                                double tau_s, double tol, int max_sweeps,
-                                               bool want_f, double (&yv)[R], double (&fr)[R]) {
+                                               bool want_f, bool warm, double (&vb)[R],
+                                               double (&yv)[R], double (&fr)[R]) {
   constexpr int NC = Geo<R>::NC;
   const bool real = c < R;
   const int cc = real ? c : 0;
@@ -506,10 +511,32 @@ __device__ __forceinline__ void polar_factored(const double* Ec, const double* s
       for (int l = 0; l < R; ++l) t = fma(Ec[p * R + l], mrow[l], t);
       g[p] = sv[p] * t;
     }
+  }
+  if (warm) {
+    // g = T vb: column i of T (held by lane i) staged in S2[i * NC + p]
+    if (real) {
+#pragma unroll
+      for (int p = 0; p < NC; ++p) S2[c * NC + p] = g[p];
+    }
+    wave_sync();
+#pragma unroll
+    for (int p = 0; p < NC; ++p) g[p] = 0.0;
+#pragma nounroll
+    for (int i = 0; i < R; ++i) {
+      const double b = vb[i];
+#pragma unroll
+      for (int p = 0; p < NC; ++p) g[p] = fma(S2[i * NC + p], b, g[p]);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = vb[i];
+    wave_sync();
+  } else {
 #pragma unroll
     for (int i = 0; i < R; ++i) v[i] = (i == c) ? 1.0 : 0.0;
   }
   jacobi_onesided<R, NC>(g, v, c, gbase, gmask, true, tol, max_sweeps);
+#pragma unroll
+  for (int i = 0; i < R; ++i) vb[i] = v[i];
   double sig2 = 0.0;
 #pragma unroll
   for (int p = 0; p < NC; ++p) sig2 = fma(g[p], g[p], sig2);

@@ -926,11 +926,12 @@ __global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float*
     }
     wave_sync();
     factor_c<R>(Cs, Ec, sv, isv, dl, c, L.gbase, L.gmask, pp.tau_c, pp.tol, pp.max_sweeps);
-    double yv[R], fr[R], m3 = 0.0;
+    double yv[R], fr[R], vb[R], m3 = 0.0;
 #pragma nounroll
     for (int step = 0; step < n_steps; ++step) {
+      // steps after the first start the SVD from the previous step's basis
       polar_factored<R>(Ec, sv, isv, wv, Hs, S, S2, dl, c, L.gbase, L.gmask, pp.tau_s, pp.tol,
-                        pp.max_sweeps, step + 1 == n_steps, yv, fr);
+                        pp.max_sweeps, step + 1 == n_steps, step > 0, vb, yv, fr);
       m3 = 0.0;
 #pragma unroll
       for (int i = 0; i < R; ++i) m3 = fma(Hs[i * R + cc], yv[i], m3);
