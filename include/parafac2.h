@@ -93,6 +93,11 @@ typedef struct {
                           replays a HIP graph captured once (per parity of the
                           V buffers and per whether the next Procrustes step is
                           fused in); 0: plain launches                        */
+  int32_t warm_polar;  /* 1: where the context keeps each subject's last
+                          eigenvector basis (parafac2_opts.keep_bases) and this
+                          build has the warm-started kernels (R <= 20), the
+                          Procrustes eigen-solves start from it; 0: they start
+                          from scratch                                        */
 } parafac2_sched;
 
 /* Options; a zero-initialised struct selects the defaults. */
@@ -110,7 +115,12 @@ typedef struct {
   parafac2_sched sched;  /* launch schedule of the context                    */
   int32_t m2_capacity;   /* mode-2 partial-sum slots planned in the workspace
                             (the largest m2_tiles a schedule may use); 0 -> 256 */
-  int32_t reserved[3];
+  int32_t keep_bases;    /* 1: each subject keeps the eigenvector basis of its
+                            last Procrustes step in the workspace (K x R x R
+                            floats, R rounded up to even; ranks <= 20) so that
+                            a schedule with warm_polar can start the next
+                            eigen-solve from it; 0: no bases are kept          */
+  int32_t reserved[1];
 } parafac2_opts;
 
 /* ABI version of the loaded library (PARAFAC2_ABI_VERSION). */
@@ -205,7 +215,8 @@ int parafac2_set_sched(parafac2_ctx* c, const parafac2_sched* sched);
 
 /* Time candidate schedules on real iterations of the context and keep the
  * fastest: tile_rounds in {1, 2, 4, 8, 16} x {static, dynamic}, then m2_tiles
- * in {16, 64, 256} (up to the capacity); the graph setting is kept.  Every
+ * in {16, 64, 256} (up to the capacity), then warm_polar in {0, 1} where
+ * bases are kept; the graph setting is kept.  Every
  * trial runs iters_per_trial (>= 1) iterations, which advance the
  * decomposition like parafac2_iterate.  chosen (host, or NULL) receives the
  * schedule kept, best_ms (host, or NULL) its milliseconds per iteration. */

@@ -39,7 +39,8 @@ class Csr(ctypes.Structure):
 
 class Sched(ctypes.Structure):
     _fields_ = [("tile_rounds", ctypes.c_int32), ("dynamic", ctypes.c_int32),
-                ("m2_tiles", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("m2_tiles", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("warm_polar", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -49,7 +50,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("tau_polar", ctypes.c_double), ("tau_pinv", ctypes.c_double),
                 ("hot_cols", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("sched", Sched), ("m2_capacity", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("keep_bases", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -145,17 +146,18 @@ def _stream_handle(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_sched(tile_rounds=0, dynamic=0, m2_tiles=0, graph=0) -> Sched:
-    return Sched(tile_rounds, dynamic, m2_tiles, graph)
+def make_sched(tile_rounds=0, dynamic=0, m2_tiles=0, graph=0, warm_polar=0) -> Sched:
+    return Sched(tile_rounds, dynamic, m2_tiles, graph, warm_polar)
 
 
 def make_opts(tau_polar=0.0, tau_pinv=0.0, hot_cols=0, max_sweeps=0, sched=None,
-              m2_capacity=0) -> Opts:
+              m2_capacity=0, keep_bases=False) -> Opts:
     o = Opts()
     o.tau_polar, o.tau_pinv, o.hot_cols, o.max_sweeps = tau_polar, tau_pinv, hot_cols, max_sweeps
     if sched is not None:
         o.sched = sched if isinstance(sched, Sched) else make_sched(**sched)
     o.m2_capacity = m2_capacity
+    o.keep_bases = 1 if keep_bases else 0
     return o
 
 

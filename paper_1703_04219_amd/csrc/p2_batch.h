@@ -46,6 +46,7 @@ struct ProbDesc {
   float* F;         // K x R x R, per subject F_k column-major
   float* M2;        // J x LDV
   float* M3;        // K x R
+  float* E;         // K x NC x R eigenvector bases of G_k (warm start), or nullptr
   double* small;    // small_layout(R)
   int64_t* iter;    // iterations completed (selects the fit ring slot)
   float* part;      // mode-2 hot partial sums: nparts slots of hot * R floats

@@ -85,8 +85,9 @@ int64_t mode2_parts(int64_t K, int R, int cap) {
 
 // Offsets of every piece of the context workspace.
 struct Plan {
-  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, V[2], F, M2, M3, small, err, part,
-      desc, tiles, m2tiles, tickets, iter, total;
+  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, V[2], F, M2, M3, E, small, err,
+      part, desc, tiles, m2tiles, tickets, iter, total;
+  bool warm = false;
   int64_t cap_tiles = 0, cap_m2 = 0;  // tile capacities of the context's own runner
   int m2cap = 0;                      // mode-2 partial-sum slots
   int hot = 0;
@@ -119,6 +120,9 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const p
   p.F = take(sizeof(float) * (size_t)K * R * R);
   p.M2 = take(sizeof(float) * J * LDV);
   p.M3 = take(sizeof(float) * (size_t)K * R);
+  p.warm = (o && o->keep_bases) && p2::warm_supported(R);
+  const int64_t NC = (R & 1) ? R + 1 : R;
+  p.E = p.warm ? take(sizeof(float) * (size_t)K * NC * R) : 0;
   p.part = take(sizeof(float) * (size_t)nparts * p.hot * R);
   p.small = take(sizeof(double) * p2::small_layout(R).total);
   p.err = take(sizeof(int) * 4);
@@ -139,6 +143,7 @@ p2::PolarParams polar_params(const parafac2_opts* o, int R) {
   pp.tol = 8.0 * 2.220446049250313e-16 * std::sqrt((double)NC);
   pp.tau_c = 1e-12;
   pp.tau_s = 1e-12;
+  pp.stop2 = 1e-10;
   pp.max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 30;
   return pp;
 }
@@ -155,6 +160,7 @@ parafac2_sched normalized(const parafac2_sched* s) {
   r.dynamic = r.dynamic ? 1 : 0;
   if (r.m2_tiles < 0) r.m2_tiles = 0;
   r.graph = r.graph ? 1 : 0;
+  r.warm_polar = r.warm_polar ? 1 : 0;
   return r;
 }
 
@@ -209,6 +215,7 @@ struct parafac2_ctx {
     d.F = at<float>(plan.F);
     d.M2 = at<float>(plan.M2);
     d.M3 = at<float>(plan.M3);
+    d.E = plan.warm ? at<float>(plan.E) : nullptr;
     d.small = small();
     d.iter = at<int64_t>(plan.iter);
     d.part = at<float>(plan.part);
@@ -338,6 +345,7 @@ int runner_plan(Runner& r) {
     std::vector<p2::Tile> seq, m2seq;
     int max_hot = 0;
     int64_t maxK = 0, maxJ = 0;
+    bool warm = r.sched.warm_polar != 0;
     for (size_t q = 0; q < g.members.size(); ++q) {
       parafac2_ctx* c = r.ctxs[g.members[q]];
       p2::ProbDesc d = c->desc();
@@ -354,6 +362,7 @@ int runner_plan(Runner& r) {
         m2seq.push_back(p2::Tile{(int32_t)q, sidx, k0, std::min(c->K, k0 + per)});
       }
       max_hot = std::max(max_hot, c->hot);
+      warm = warm && c->plan.warm;
       maxK = std::max(maxK, c->K);
       maxJ = std::max(maxJ, c->J);
     }
@@ -380,6 +389,7 @@ int runner_plan(Runner& r) {
     b.nm2 = (int)m2tiles.size();
     b.tickets = g.tickets;
     b.dynamic = r.sched.dynamic;
+    b.warm = warm ? 1 : 0;
     b.max_hot = max_hot;
     b.maxK = maxK;
     b.maxJ = maxJ;
@@ -599,6 +609,21 @@ int runner_autotune(Runner& r, int32_t iters, parafac2_sched* chosen, double* be
     if (m2 > maxcap) continue;
     parafac2_sched sc = best;
     sc.m2_tiles = m2;
+    double t = 0;
+    rc = trial(sc, &t);
+    if (rc != P2_OK) break;
+    if (t < best_t) {
+      best_t = t;
+      best = normalized(&sc);
+    }
+  }
+  bool any_warm = false;
+  for (parafac2_ctx* c : r.ctxs) any_warm = any_warm || c->plan.warm;
+  for (int wp = 0; wp < 2 && any_warm; ++wp) {
+    if (rc != P2_OK) break;
+    parafac2_sched sc = best;
+    if (sc.warm_polar == wp) continue;
+    sc.warm_polar = wp;
     double t = 0;
     rc = trial(sc, &t);
     if (rc != P2_OK) break;
@@ -877,6 +902,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   INIT_TRY(p2::run_encode(X->subj_ptr, X->row_ptr, X->col, X->val, X->K, X->nnz,
                           c->at<int32_t>(plan.rank), c->at<uint16_t>(plan.rstart),
                           c->at<uint16_t>(plan.col16), c->at<float>(plan.val), sm + SL.nx2, s));
+  if (plan.warm) INIT_TRY(p2::run_eye_basis(c->at<float>(plan.E), X->K, R, s));
   INIT_TRY(p2::run_fill_f32(c->V(0), X->J * c->LDV, 0.f, s));
   INIT_TRY(p2::run_fill_f32(c->V(1), X->J * c->LDV, 0.f, s));
   INIT_TRY(p2::run_permute_rows(V, c->V(0), X->J, R, R, c->LDV, c->at<int32_t>(plan.rank), s));

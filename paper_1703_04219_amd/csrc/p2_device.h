@@ -240,14 +240,17 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // For a symmetric PSD input the rotations need not be accumulated (ACCUM =
 // false): G^2 = sum_j g_j g_j^T with orthogonal g_j, so g_j / ||g_j|| is an
 // eigenvector of G with eigenvalue ||g_j||.
-// A group stops (no rotation, no swap) after a sweep whose rotations were all
-// below 1e-9 in relative size -- Jacobi converges quadratically, so the
-// columns are then orthogonal to working precision -- which keeps its result
-// independent of the other groups of the wavefront.
+// A group stops (no rotation, no swap) after a sweep in which no pair had
+// gamma^2 > stop2 * alpha * beta (gamma the pair's inner product, alpha and
+// beta its squared norms; stop2 = 1e-10 by default, rotations below 1e-5).
+// Jacobi converges quadratically, so the columns are then orthogonal to about
+// stop2 relative, far below the FP32 precision of every output.  Stopping per
+// group keeps its result independent of the other groups of the wavefront.
 // ---------------------------------------------------------------------------
 template <int R, int N, bool ODD, bool ACCUM>
 __device__ __forceinline__ void jacobi_step(double (&g)[N], double (&v)[R], int j, bool lane_odd,
-                                            bool done, double tol2, bool& rot, bool& big) {
+                                            bool done, double tol2, double stop2, bool& rot,
+                                            bool& big) {
   constexpr int NC = Geo<R>::NC;
   constexpr bool kKeepPartner = N <= 20;
   const int partner = ODD ? (lane_odd ? j + 1 : j - 1) : (j ^ 1);
@@ -278,7 +281,7 @@ __device__ __forceinline__ void jacobi_step(double (&g)[N], double (&v)[R], int 
     cs = rsq_nr(fma(t, t, 1.0));
     sn = cs * t;
     rot = true;
-    if (g2 > 1e-18 * ab) big = true;
+    if (g2 > stop2 * ab) big = true;
   }
   // rotate and swap: the lower position receives s x + c y, the upper c x - s y;
   // a lane that does not take part keeps its column (coefficients 1, 0)
@@ -305,7 +308,7 @@ __device__ __forceinline__ void jacobi_step(double (&g)[N], double (&v)[R], int 
 template <int R, int N = R, bool ACCUM = true>
 __device__ __forceinline__ void jacobi_onesided(double (&g)[N], double (&v)[R], int j, int gbase,
                                                 uint64_t gmask, bool live, double tol,
-                                                int max_sweeps) {
+                                                double stop2, int max_sweeps) {
   constexpr int NC = Geo<R>::NC;
   static_assert(NC % 2 == 0, "groups have an even number of lanes");
   const bool lane_odd = (j & 1) != 0;
@@ -317,8 +320,8 @@ __device__ __forceinline__ void jacobi_onesided(double (&g)[N], double (&v)[R], 
     bool rot = false, big = false;
 #pragma nounroll
     for (int step = 0; step < NC; step += 2) {
-      jacobi_step<R, N, false, ACCUM>(g, v, j, lane_odd, done, tol2, rot, big);
-      jacobi_step<R, N, true, ACCUM>(g, v, j, lane_odd, done, tol2, rot, big);
+      jacobi_step<R, N, false, ACCUM>(g, v, j, lane_odd, done, tol2, stop2, rot, big);
+      jacobi_step<R, N, true, ACCUM>(g, v, j, lane_odd, done, tol2, stop2, rot, big);
     }
     (void)rot;
     if ((__ballot(big) & gmask) == 0ull) done = true;
@@ -337,15 +340,32 @@ __device__ __forceinline__ void jacobi_onesided(double (&g)[N], double (&v)[R], 
 // of W (R doubles), both in the group's LDS; Hs is H (R x R, row-major) in
 // the block's LDS.  On exit lane c (< R) holds F(:, c) in f and (Y V)(:, c)
 // in y.  S is the group's LDS scratch of NC x R doubles, dl of NC doubles.
+//
+// With WARM, E is the subject's eigenvector basis of G from its previous
+// Procrustes step: NC columns of R floats, column p at E + p R (the identity,
+// plus a zero column for odd R, before the first step).  With E the solve is
+// warm-started: Jacobi (accumulating its rotations) starts from the columns
+// G E, which are already close to orthogonal when G moved little since the
+// last iteration.  The accumulated basis is orthonormal to the FP32 rounding
+// of the stored E; one Newton-Schulz step V (3I - V^T V) / 2 restores FP64
+// orthonormality before it is used and written back, so rounding does not
+// build up over iterations.  Without WARM, Jacobi starts from G itself and does
+// not accumulate: for a symmetric PSD G the converged columns g_p are
+// lambda_p times the eigenvectors.
 // ---------------------------------------------------------------------------
-template <int R>
+template <int R, bool WARM>
 __device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, const double* Hs,
-                                          double* S, double* dl, int c, int gbase, uint64_t gmask,
-                                          bool live, double tau, double tol, int max_sweeps,
+                                          double* S, double* dl, float* __restrict__ E, int c,
+                                          int gbase, uint64_t gmask, bool live, double tau,
+                                          double tol, double stop2, int max_sweeps,
                                           double (&f)[R], double (&y)[R]) {
   constexpr int NC = Geo<R>::NC;
   const bool real = c < R;
   const int cc = real ? c : 0;
+  constexpr bool warm = WARM;
+  double g[R], v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = warm ? (double)E[c * R + i] : ((i == c) ? 1.0 : 0.0);
   // T(c, :) = C(c, :) M^T,   T(c, j) = sum_l C(c, l) w(l) H(j, l)
   {
     double cw[R];
@@ -361,25 +381,36 @@ __device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, con
   }
   wave_sync();
   // g = G(:, c) = sum_l H(:, l) w(l) T(l, c)
-  double g[R], v[R];
-  {
-    double u[R];
 #pragma unroll
-    for (int l = 0; l < R; ++l) u[l] = real ? w[l] * S[l * R + cc] : 0.0;
+  for (int i = 0; i < R; ++i) g[i] = 0.0;
+#pragma nounroll
+  for (int l = 0; l < R; ++l) {
+    const double u = real ? w[l] * S[l * R + cc] : 0.0;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      double t = 0.0;
-#pragma unroll
-      for (int l = 0; l < R; ++l) t = fma(Hs[i * R + l], u[l], t);
-      g[i] = t;
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = (i == c) ? 1.0 : 0.0;
+    for (int i = 0; i < R; ++i) g[i] = fma(Hs[i * R + l], u, g[i]);
   }
   wave_sync();
-  jacobi_onesided<R, R, false>(g, v, c, gbase, gmask, live, tol, max_sweeps);
-  // eigenvalue ||g|| and eigenvector g / ||g|| at this position, and the
-  // group's largest eigenvalue
+  if constexpr (warm) {
+    // g = G v, with the columns of G staged in S
+    if (real) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) S[c * R + i] = g[i];
+    }
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < R; ++i) g[i] = 0.0;
+#pragma nounroll
+    for (int q = 0; q < R; ++q) {
+      const double vq = v[q];
+#pragma unroll
+      for (int i = 0; i < R; ++i) g[i] = fma(S[q * R + i], vq, g[i]);
+    }
+    wave_sync();
+    jacobi_onesided<R, R, true>(g, v, c, gbase, gmask, live, tol, stop2, max_sweeps);
+  } else {
+    jacobi_onesided<R, R, false>(g, v, c, gbase, gmask, live, tol, stop2, max_sweeps);
+  }
+  // eigenvalue ||g|| at this position and the group's largest eigenvalue
   double lam2 = 0.0;
 #pragma unroll
   for (int i = 0; i < R; ++i) lam2 = fma(g[i], g[i], lam2);
@@ -391,12 +422,38 @@ __device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, con
   wave_sync();
   const bool keep = lam > tau * lmax && lam > 0.0;
   const double d = keep ? 1.0 / sqrt(lam) : 0.0;
-  const double inv_lam = keep ? 1.0 / lam : 0.0;
+  if constexpr (warm) {
+    // eigenvectors v, made orthonormal in FP64 and kept for the next step
 #pragma unroll
-  for (int i = 0; i < R; ++i) S[c * R + i] = g[i] * inv_lam;
+    for (int i = 0; i < R; ++i) S[c * R + i] = v[i];
+    wave_sync();
+    double acc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] = 0.0;
+#pragma nounroll
+    for (int q = 0; q < NC; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) t = fma(S[q * R + i], v[i], t);
+#pragma unroll
+      for (int i = 0; i < R; ++i) acc[i] = fma(t, S[q * R + i], acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = fma(1.5, v[i], -0.5 * acc[i]);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      E[c * R + i] = (float)v[i];
+      S[c * R + i] = keep ? v[i] : 0.0;
+    }
+  } else {
+    const double inv_lam = keep ? 1.0 / lam : 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) S[c * R + i] = g[i] * inv_lam;
+  }
   dl[c] = d;
   wave_sync();
-  // F(:, c) = sum_p d_p v_p (v_p . M(:, c)),   M(:, c) = H(:, c) w(c)
+  // F(:, c) = sum_p d_p u_p (u_p . M(:, c)),   M(:, c) = H(:, c) w(c)
   {
     double m[R];
 #pragma unroll
@@ -455,7 +512,7 @@ __device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, con
 template <int R>
 __device__ __forceinline__ void factor_c(const double* Cs, double* Ec, double* sv, double* isv,
                                          double* dl, int c, int gbase, uint64_t gmask,
-                                         double tau_c, double tol, int max_sweeps) {
+                                         double tau_c, double tol, double stop2, int max_sweeps) {
   constexpr int NC = Geo<R>::NC;
   double g[R], v[R];
 #pragma unroll
@@ -463,7 +520,7 @@ __device__ __forceinline__ void factor_c(const double* Cs, double* Ec, double* s
     g[i] = (c < R) ? Cs[i * R + c] : 0.0;
     v[i] = (i == c) ? 1.0 : 0.0;
   }
-  jacobi_onesided<R>(g, v, c, gbase, gmask, true, tol, max_sweeps);
+  jacobi_onesided<R>(g, v, c, gbase, gmask, true, tol, stop2, max_sweeps);
   double lam = 0.0;
 #pragma unroll
   for (int i = 0; i < R; ++i) lam = fma(v[i], g[i], lam);
@@ -492,8 +549,9 @@ __device__ __forceinline__ void polar_factored(const double* Ec, const double* s
                                                const double* isv, const double* w,
                                                const double* Hs, double* S, double* S2,
                                                double* dl, int c, int gbase, uint64_t gmask,
-                                               double tau_s, double tol, int max_sweeps,
-                                               bool want_f, bool warm, double (&vb)[R],
+                                               double tau_s, double tol, double stop2,
+                                               int max_sweeps, bool want_f, bool warm,
+                                               double (&vb)[R],
                                                double (&yv)[R], double (&fr)[R]) {
   constexpr int NC = Geo<R>::NC;
   const bool real = c < R;
@@ -534,7 +592,7 @@ __device__ __forceinline__ void polar_factored(const double* Ec, const double* s
 #pragma unroll
     for (int i = 0; i < R; ++i) v[i] = (i == c) ? 1.0 : 0.0;
   }
-  jacobi_onesided<R, NC>(g, v, c, gbase, gmask, true, tol, max_sweeps);
+  jacobi_onesided<R, NC>(g, v, c, gbase, gmask, true, tol, stop2, max_sweeps);
 #pragma unroll
   for (int i = 0; i < R; ++i) vb[i] = v[i];
   double sig2 = 0.0;

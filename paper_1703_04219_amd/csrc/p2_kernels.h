@@ -17,10 +17,13 @@ struct PolarParams {
   double tol;        // Jacobi rotation threshold |g_p . g_q| > tol ||g_p|| ||g_q||
   double tau_c;      // relative eigenvalue cut of C = A^T A in the factored polar
   double tau_s;      // relative singular value cut of T in the factored polar
+  double stop2;      // a Jacobi sweep with no pair above gamma^2 > stop2 alpha beta ends the solve
   int max_sweeps;
 };
 
 bool rank_supported(int R);
+// Whether the warm-started Procrustes kernels are built for rank R.
+bool warm_supported(int R);
 int lds_bytes_per_cu();
 
 // Largest number of hot columns whose mode-2 partial sums fit the LDS budget.
@@ -37,6 +40,8 @@ struct BatchView {
   int nm2 = 0;
   int* tickets = nullptr;          // kTicketKinds * kBins counters (dynamic schedule)
   int dynamic = 0;
+  int warm = 0;                    // warm-started polar (every problem has its basis E);
+                                   // plan_launch clears it for ranks built without it
   int max_hot = 0;                 // LDS hot columns of the mode-2 launch (max over problems)
   int64_t maxK = 0, maxJ = 0;
   // filled by plan_launch (needs the current device; nothing but launches
@@ -88,6 +93,8 @@ hipError_t run_permute_rows(const float* src, float* dst, int64_t J, int R, int 
                             int ld_dst, const int32_t* map, hipStream_t s);
 hipError_t run_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t run_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+// K identity bases (NC x R floats each, NC = R rounded up to even)
+hipError_t run_eye_basis(float* E, int64_t K, int R, hipStream_t s);
 hipError_t run_model_prep(int R, const double* VtV, const double* H, double* HtH, double* N3,
                           double* N3p, const PolarParams& pp, hipStream_t s);
 hipError_t run_iota(int32_t* p, int64_t n, hipStream_t s);

@@ -139,7 +139,7 @@ __device__ __forceinline__ int claim_tile(int ntiles, int* tickets, int i, int* 
 // F_k and (Y_k V) from the polar factor (objective (procrustes_obj)), mode-1
 // partial (Y_k V) S_k added into M1 (equation (mttkrp1_2)).
 // ---------------------------------------------------------------------------
-template <int R>
+template <int R, bool WARM>
 __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
                                                 const Tile* __restrict__ T, int ntiles,
                                                 int* tickets, int parity, PolarParams pp) {
@@ -197,7 +197,9 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
         }
         wave_sync();
         double f[R], y[R];
-        polar_rxr<R>(Cs, wv, Hs, S, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
+        float* Ek = WARM ? D.E + k * (Geo<R>::NC * R) : nullptr;
+        polar_rxr<R, WARM>(Cs, wv, Hs, S, dl, Ek, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
+                     pp.stop2,
                      pp.max_sweeps, f, y);
         if (c < R) {
           float* Fk = F + (size_t)k * R * R + (size_t)c * R;
@@ -225,7 +227,7 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
 // do_next, the next iteration's Procrustes step and mode-1 partial from
 // C'_k = A'_k^T A'_k.
 // ---------------------------------------------------------------------------
-template <int R>
+template <int R, bool WARM>
 __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
                                                 const Tile* __restrict__ T, int ntiles,
                                                 int* tickets, int parity, int do_next,
@@ -340,7 +342,9 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
           }
           wave_sync();
           double f[R], y[R];
-          polar_rxr<R>(SF, wv, Hs, SP, dl, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
+          float* Ek = WARM ? D.E + k * (Geo<R>::NC * R) : nullptr;
+          polar_rxr<R, WARM>(SF, wv, Hs, SP, dl, Ek, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
+                       pp.stop2,
                        pp.max_sweeps, f, y);
           if (real) {
             float* Fk = F + (size_t)k * R * R + (size_t)c * R;
@@ -582,7 +586,8 @@ __device__ void pinv_cols(const double (&ncol)[R], int c, double* S, double* dl,
     v[i] = (i == c) ? 1.0 : 0.0;
   }
   const uint64_t gmask = (NC == 64) ? ~0ull : ((1ull << NC) - 1ull);
-  jacobi_onesided<R, R, false>(g, v, c, 0, gmask, c < NC, tol, max_sweeps);
+  // the normal-equation solves are tiny: run them to full FP64 convergence
+  jacobi_onesided<R, R, false>(g, v, c, 0, gmask, c < NC, tol, 1e-18, max_sweeps);
   double lam2 = 0.0;
 #pragma unroll
   for (int i = 0; i < R; ++i) lam2 = fma(g[i], g[i], lam2);
@@ -925,13 +930,14 @@ __global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float*
       }
     }
     wave_sync();
-    factor_c<R>(Cs, Ec, sv, isv, dl, c, L.gbase, L.gmask, pp.tau_c, pp.tol, pp.max_sweeps);
+    factor_c<R>(Cs, Ec, sv, isv, dl, c, L.gbase, L.gmask, pp.tau_c, pp.tol, pp.stop2,
+                pp.max_sweeps);
     double yv[R], fr[R], vb[R], m3 = 0.0;
 #pragma nounroll
     for (int step = 0; step < n_steps; ++step) {
       // steps after the first start the SVD from the previous step's basis
       polar_factored<R>(Ec, sv, isv, wv, Hs, S, S2, dl, c, L.gbase, L.gmask, pp.tau_s, pp.tol,
-                        pp.max_sweeps, step + 1 == n_steps, step > 0, vb, yv, fr);
+                        pp.stop2, pp.max_sweeps, step + 1 == n_steps, step > 0, vb, yv, fr);
       m3 = 0.0;
 #pragma unroll
       for (int i = 0; i < R; ++i) m3 = fma(Hs[i * R + cc], yv[i], m3);
@@ -1142,6 +1148,18 @@ __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
     p[t] = v;
 }
 
+// Per-subject start bases of the warm-started polar: column p of subject k is
+// e_p (p < R) or zero (the padding column of odd R).
+__global__ void k_eye_basis(float* __restrict__ E, int64_t K, int R, int NC) {
+  const int64_t per = (int64_t)NC * R;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < K * per;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = t % per;
+    const int p = (int)(q / R), i = (int)(q % R);
+    E[t] = (p == i) ? 1.f : 0.f;
+  }
+}
+
 __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x)
@@ -1303,15 +1321,34 @@ hipError_t resident_grid(Kern k, int threads, size_t lds, int want, int* grid) {
   return hipSuccess;
 }
 
+// Ranks whose warm-started polar kernels are built (the accumulated Jacobi
+// basis must fit the register file next to the rest of the kernel).
+constexpr int kWarmMaxR = 20;
+
 template <int R>
 hipError_t plan_t(BatchView& b) {
   if (b.ntiles % kBins != 0 || b.nm2 % kBins != 0) return hipErrorInvalidValue;
   if (b.max_hot < 0 || b.max_hot > max_hot_t<R>()) return hipErrorInvalidValue;
-  hipError_t e = resident_grid(k_alpha<R>, alpha_threads<R>(), alpha_lds<R>(), b.ntiles,
-                               &b.grid_alpha);
-  if (e != hipSuccess) return e;
-  e = resident_grid(k_gamma<R>, gamma_threads<R>(), gamma_lds<R>(), b.ntiles, &b.grid_gamma);
-  if (e != hipSuccess) return e;
+  if (R > kWarmMaxR) b.warm = 0;
+  hipError_t e;
+  if constexpr (R <= kWarmMaxR) {
+    if (b.warm) {
+      e = resident_grid(k_alpha<R, true>, alpha_threads<R>(), alpha_lds<R>(), b.ntiles,
+                        &b.grid_alpha);
+      if (e != hipSuccess) return e;
+      e = resident_grid(k_gamma<R, true>, gamma_threads<R>(), gamma_lds<R>(), b.ntiles,
+                        &b.grid_gamma);
+      if (e != hipSuccess) return e;
+    }
+  }
+  if (!b.warm) {
+    e = resident_grid(k_alpha<R, false>, alpha_threads<R>(), alpha_lds<R>(), b.ntiles,
+                      &b.grid_alpha);
+    if (e != hipSuccess) return e;
+    e = resident_grid(k_gamma<R, false>, gamma_threads<R>(), gamma_lds<R>(), b.ntiles,
+                      &b.grid_gamma);
+    if (e != hipSuccess) return e;
+  }
   return resident_grid(k_mode2<R>, mode2_threads<R>(), mode2_lds<R>(b.max_hot), b.nm2,
                        &b.grid_mode2);
 }
@@ -1320,19 +1357,38 @@ inline int* tickets_of(const BatchView& b, int kind) {
   return b.dynamic ? b.tickets + kind * kBins : nullptr;
 }
 
+template <int R, bool WARM>
+hipError_t alpha_w(const BatchView& b, int parity, const PolarParams& pp, hipStream_t s) {
+  hipLaunchKernelGGL((k_alpha<R, WARM>), dim3(b.grid_alpha), dim3(alpha_threads<R>()),
+                     alpha_lds<R>(), s, b.desc, b.tiles, b.ntiles, tickets_of(b, kTicketAlpha),
+                     parity, pp);
+  return hipGetLastError();
+}
+
+template <int R, bool WARM>
+hipError_t gamma_w(const BatchView& b, int parity, int do_next, const PolarParams& pp,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((k_gamma<R, WARM>), dim3(b.grid_gamma), dim3(gamma_threads<R>()),
+                     gamma_lds<R>(), s, b.desc, b.tiles, b.ntiles, tickets_of(b, kTicketGamma),
+                     parity, do_next, pp);
+  return hipGetLastError();
+}
+
 template <int R>
 hipError_t alpha_t(const BatchView& b, int parity, const PolarParams& pp, hipStream_t s) {
-  hipLaunchKernelGGL(k_alpha<R>, dim3(b.grid_alpha), dim3(alpha_threads<R>()), alpha_lds<R>(), s,
-                     b.desc, b.tiles, b.ntiles, tickets_of(b, kTicketAlpha), parity, pp);
-  return hipGetLastError();
+  if constexpr (R <= kWarmMaxR) {
+    if (b.warm) return alpha_w<R, true>(b, parity, pp, s);
+  }
+  return alpha_w<R, false>(b, parity, pp, s);
 }
 
 template <int R>
 hipError_t gamma_t(const BatchView& b, int parity, int do_next, const PolarParams& pp,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_gamma<R>, dim3(b.grid_gamma), dim3(gamma_threads<R>()), gamma_lds<R>(), s,
-                     b.desc, b.tiles, b.ntiles, tickets_of(b, kTicketGamma), parity, do_next, pp);
-  return hipGetLastError();
+  if constexpr (R <= kWarmMaxR) {
+    if (b.warm) return gamma_w<R, true>(b, parity, do_next, pp, s);
+  }
+  return gamma_w<R, false>(b, parity, do_next, pp, s);
 }
 
 template <int R>
@@ -1513,6 +1569,12 @@ hipError_t run_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t run_eye_basis(float* E, int64_t K, int R, hipStream_t s) {
+  hipLaunchKernelGGL(k_eye_basis, dim3(grid1(K * R * R)), dim3(256), 0, s, E, K, R,
+                     (R & 1) ? R + 1 : R);
+  return hipGetLastError();
+}
+
 hipError_t run_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_f32, dim3(grid1(n)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
@@ -1529,6 +1591,8 @@ hipError_t run_iota(int32_t* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_iota, dim3(grid1(n)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
+
+bool warm_supported(int R) { return rank_supported(R) && R <= kWarmMaxR; }
 
 int polar_tile_unit(int R) {
   switch (R) {

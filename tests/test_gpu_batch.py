@@ -42,7 +42,7 @@ def _problems(n=6, k_scale=0.04):
 
 
 def _ctx(X, R, H0, V0, W0, **sched):
-    opts = B.make_opts(sched=B.make_sched(**sched)) if sched else None
+    opts = B.make_opts(sched=B.make_sched(**sched), keep_bases=True) if sched else None
     return B.Context(B.DeviceSlices.from_slices(X), R, H0, V0, W0, opts)
 
 
@@ -90,7 +90,7 @@ def test_batch_equals_one_problem_at_a_time(sched):
 
 @pytest.mark.parametrize("sched", [
     dict(tile_rounds=1), dict(tile_rounds=16), dict(dynamic=1), dict(dynamic=1, tile_rounds=2),
-    dict(m2_tiles=8), dict(graph=1), dict(graph=1, dynamic=1)])
+    dict(m2_tiles=8), dict(graph=1), dict(graph=1, dynamic=1), dict(warm_polar=1)])
 def test_schedules_agree(sched):
     X, R = gen_config(2, k_limit=6000)
     H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, 2, 1])
@@ -143,6 +143,26 @@ def test_autotune_keeps_the_iteration():
     assert sc.tile_rounds in (1, 2, 4, 8, 16) and sc.dynamic in (0, 1) and ms > 0
     f = batch.iterate(5)
     assert np.all(np.diff(f, axis=0) >= -1e-6)
+
+
+@pytest.mark.parametrize("R", [3, 10, 20])
+def test_warm_started_polar_matches_cold_over_many_iterations(R):
+    # the kept eigenvector bases only change where each eigen-solve starts:
+    # fits agree with the cold path over 30 iterations, and with the oracle
+    from datagen import gen_slices
+    from datagen.synth import _poisson_plus_one
+    X = gen_slices(400, 200, (R, R + 30), _poisson_plus_one(2.0), "zipf", [7700 + R])
+    H0, V0, W0 = gen_init(X.J, X.K, R, [7700 + R, 1])
+    warm = _ctx(X, R, H0, V0, W0, warm_polar=1)
+    cold = _ctx(X, R, H0, V0, W0)
+    fw, fc = warm.iterate(30), cold.iterate(30)
+    Xs = O.slices_to_list(X.subj_ptr, X.row_ptr, X.col, X.val, X.J)
+    _, _, _, hist = O.run(Xs, H0, V0, W0, 30, dense_loss=False)
+    fo = np.array([h["fit"] for h in hist])
+    print(f"R={R} warm-cold {np.abs(fw - fc).max():.2e} warm-oracle {np.abs(fw - fo).max():.2e}",
+          flush=True)
+    assert np.abs(fw - fc).max() <= 1e-5
+    assert np.abs(fw - fo).max() <= 1e-5
 
 
 def test_batch_refuses_contexts_out_of_step():
