@@ -61,6 +61,21 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_bytes": n * 4, "launches": 3}), flush=True)
 
 
+KERNEL_SOURCES = ("paper_1703_04219_amd/csrc/p2_kernels.hip", "paper_1703_04219_amd/csrc/p2_device.h",
+                  "paper_1703_04219_amd/csrc/p2_batch.h")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the kernel sources: counter readings taken on other sources
+    no longer describe the kernels that run."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def stream_bytes(X, R: int) -> dict:
     """Algorithmic HBM bytes of one pass over the re-encoded slices and the
     per-subject state, as used by the per-iteration kernels."""
@@ -333,7 +348,9 @@ def main():
     tfile = os.path.join(ROOT, "profiles", f"traffic_k_{dom}_c{a.config}.json")
     if os.path.exists(tfile) and a.k_limit is None:
         with open(tfile) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+            rec = json.load(f)
+        if rec.get("source_sha256") == kernel_source_hash():
+            traffic = rec.get("bytes_per_launch")
     roof = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),

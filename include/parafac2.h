@@ -114,7 +114,7 @@ typedef struct {
   int32_t max_sweeps;/* cap on Jacobi sweeps per R x R eigenproblem; 0 -> 30 */
   parafac2_sched sched;  /* launch schedule of the context                    */
   int32_t m2_capacity;   /* mode-2 partial-sum slots planned in the workspace
-                            (the largest m2_tiles a schedule may use); 0 -> 256 */
+                            (the largest m2_tiles a schedule may use); 0 -> 512 */
   int32_t keep_bases;    /* 1: each subject keeps the eigenvector basis of its
                             last Procrustes step in the workspace (K x R x R
                             floats, R rounded up to even; ranks <= 20) so that
@@ -215,7 +215,7 @@ int parafac2_set_sched(parafac2_ctx* c, const parafac2_sched* sched);
 
 /* Time candidate schedules on real iterations of the context and keep the
  * fastest: tile_rounds in {1, 2, 4, 8, 16} x {static, dynamic}, then m2_tiles
- * in {16, 64, 256} (up to the capacity), then warm_polar in {0, 1} where
+ * in {128, 256, 512} (up to the capacity), then warm_polar in {0, 1} where
  * bases are kept; the graph setting is kept.  Every
  * trial runs iters_per_trial (>= 1) iterations, which advance the
  * decomposition like parafac2_iterate.  chosen (host, or NULL) receives the

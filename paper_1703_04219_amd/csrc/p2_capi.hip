@@ -62,7 +62,7 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 inline int ldv_of(int R) { return (R + 3) & ~3; }
 
 constexpr int kDefaultRounds = 4;
-constexpr int kDefaultM2Capacity = 256;
+constexpr int kDefaultM2Capacity = 512;
 constexpr int kMaxM2Capacity = 4096;
 
 int m2_capacity(const parafac2_opts* o) {
@@ -603,7 +603,8 @@ int runner_autotune(Runner& r, int32_t iters, parafac2_sched* chosen, double* be
     }
   int maxcap = 0;
   for (parafac2_ctx* c : r.ctxs) maxcap = std::max(maxcap, c->plan.m2cap);
-  const int m2s[] = {16, 64, 256};
+  // mode-2 tiles per problem; fewer than the device's 256 CUs leave CUs idle
+  const int m2s[] = {128, 256, 512};
   for (int m2 : m2s) {
     if (rc != P2_OK) break;
     if (m2 > maxcap) continue;
