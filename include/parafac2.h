@@ -93,6 +93,12 @@ typedef struct {
                           replays a HIP graph captured once (per parity of the
                           V buffers and per whether the next Procrustes step is
                           fused in); 0: plain launches                        */
+  int32_t m2_threads;  /* mode-2 workgroup size (multiple of 64, <= 1024);
+                          0 -> the rank's default                             */
+  int32_t m2_blocks;   /* mode-2 workgroups meant to share a CU: each keeps
+                          the hot-column partial sums that fit its 1/m2_blocks
+                          share of the LDS (fewer hot columns, more waves in
+                          flight); 0 -> 1                                    */
   int32_t warm_polar;  /* 1: where the context keeps each subject's last
                           eigenvector basis (parafac2_opts.keep_bases) and this
                           build has the warm-started kernels (R <= 20), the
@@ -215,8 +221,9 @@ int parafac2_set_sched(parafac2_ctx* c, const parafac2_sched* sched);
 
 /* Time candidate schedules on real iterations of the context and keep the
  * fastest: tile_rounds in {1, 2, 4, 8, 16} x {static, dynamic}, then m2_tiles
- * in {128, 256, 512} (up to the capacity), then warm_polar in {0, 1} where
- * bases are kept; the graph setting is kept.  Every
+ * in {128, 256, 512} (up to the capacity), then (m2_threads, m2_blocks) in
+ * {(default, 1), (512, 2), (768, 2), (512, 3), (256, 4)}, then warm_polar in
+ * {0, 1} where bases are kept; the graph setting is kept.  Every
  * trial runs iters_per_trial (>= 1) iterations, which advance the
  * decomposition like parafac2_iterate.  chosen (host, or NULL) receives the
  * schedule kept, best_ms (host, or NULL) its milliseconds per iteration. */

@@ -40,6 +40,7 @@ class Csr(ctypes.Structure):
 class Sched(ctypes.Structure):
     _fields_ = [("tile_rounds", ctypes.c_int32), ("dynamic", ctypes.c_int32),
                 ("m2_tiles", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("m2_threads", ctypes.c_int32), ("m2_blocks", ctypes.c_int32),
                 ("warm_polar", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
@@ -146,8 +147,9 @@ def _stream_handle(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_sched(tile_rounds=0, dynamic=0, m2_tiles=0, graph=0, warm_polar=0) -> Sched:
-    return Sched(tile_rounds, dynamic, m2_tiles, graph, warm_polar)
+def make_sched(tile_rounds=0, dynamic=0, m2_tiles=0, graph=0, m2_threads=0, m2_blocks=0,
+               warm_polar=0) -> Sched:
+    return Sched(tile_rounds, dynamic, m2_tiles, graph, m2_threads, m2_blocks, warm_polar)
 
 
 def make_opts(tau_polar=0.0, tau_pinv=0.0, hot_cols=0, max_sweeps=0, sched=None,

@@ -161,6 +161,8 @@ parafac2_sched normalized(const parafac2_sched* s) {
   if (r.m2_tiles < 0) r.m2_tiles = 0;
   r.graph = r.graph ? 1 : 0;
   r.warm_polar = r.warm_polar ? 1 : 0;
+  r.m2_threads = std::max(0, std::min(r.m2_threads, 1024)) / 64 * 64;
+  r.m2_blocks = std::max(0, std::min(r.m2_blocks, 8));
   return r;
 }
 
@@ -391,6 +393,8 @@ int runner_plan(Runner& r) {
     b.dynamic = r.sched.dynamic;
     b.warm = warm ? 1 : 0;
     b.max_hot = max_hot;
+    b.m2_threads = r.sched.m2_threads;
+    b.m2_blocks = r.sched.m2_blocks;
     b.maxK = maxK;
     b.maxJ = maxJ;
     HIP_TRY(p2::plan_launch(b));
@@ -610,6 +614,21 @@ int runner_autotune(Runner& r, int32_t iters, parafac2_sched* chosen, double* be
     if (m2 > maxcap) continue;
     parafac2_sched sc = best;
     sc.m2_tiles = m2;
+    double t = 0;
+    rc = trial(sc, &t);
+    if (rc != P2_OK) break;
+    if (t < best_t) {
+      best_t = t;
+      best = normalized(&sc);
+    }
+  }
+  const int m2shapes[][2] = {{0, 1}, {512, 2}, {768, 2}, {512, 3}, {256, 4}};
+  for (const auto& sh : m2shapes) {
+    if (rc != P2_OK) break;
+    parafac2_sched sc = best;
+    if (sc.m2_threads == sh[0] && std::max(sc.m2_blocks, 1) == sh[1]) continue;
+    sc.m2_threads = sh[0];
+    sc.m2_blocks = sh[1];
     double t = 0;
     rc = trial(sc, &t);
     if (rc != P2_OK) break;

@@ -212,21 +212,18 @@ __device__ __forceinline__ double partner_of(double x, bool lane_odd) {
   }
 }
 
-// 1/sqrt(x) and 1/x in FP64 from the hardware approximations plus two
-// Newton steps each (rotation parameters need c^2 + s^2 = 1 to working
-// precision, not correct rounding).
+// 1/sqrt(x) and 1/x in FP64 from the hardware approximations plus one Newton
+// step each.  The rotation parameters only need c^2 + s^2 = 1 to far below
+// FP32 precision: an error e per rotation scales a column by 1 + e, and a
+// solve makes a few hundred rotations; the refined values are good to about
+// the square of the hardware approximation's relative error.
 __device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);
 }
 __device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = fma(y, fma(-x, y, 1.0), y);
-  y = fma(y, fma(-x, y, 1.0), y);
-  return y;
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
 }
 
 // ---------------------------------------------------------------------------
@@ -247,24 +244,31 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // stop2 relative, far below the FP32 precision of every output.  Stopping per
 // group keeps its result independent of the other groups of the wavefront.
 // ---------------------------------------------------------------------------
+// own2 is this position's squared column norm, carried from step to step
+// (updated from the rotation instead of recomputed; the sweep loop recomputes
+// it at the start of every sweep).
 template <int R, int N, bool ODD, bool ACCUM>
-__device__ __forceinline__ void jacobi_step(double (&g)[N], double (&v)[R], int j, bool lane_odd,
-                                            bool done, double tol2, double stop2, bool& rot,
-                                            bool& big) {
+__device__ __forceinline__ void jacobi_step(double (&g)[N], double (&v)[R], double& own2, int j,
+                                            bool lane_odd, bool done, double tol2, double stop2,
+                                            bool& rot, bool& big) {
   constexpr int NC = Geo<R>::NC;
   constexpr bool kKeepPartner = N <= 20;
   const int partner = ODD ? (lane_odd ? j + 1 : j - 1) : (j ^ 1);
   const bool act = !done && (!ODD || (j != 0 && j != NC - 1));
   const bool lower = j < partner;
-  double own2 = 0.0, gam = 0.0;
+  // the inner product with the partner's column, in two independent chains
+  double gam0 = 0.0, gam1 = 0.0;
   double pg[kKeepPartner ? N : 1];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     const double p = partner_of<ODD>(g[i], lane_odd);
     if constexpr (kKeepPartner) pg[i] = p;
-    own2 = fma(g[i], g[i], own2);
-    gam = fma(g[i], p, gam);
+    if (i & 1)
+      gam1 = fma(g[i], p, gam1);
+    else
+      gam0 = fma(g[i], p, gam0);
   }
+  const double gam = gam0 + gam1;
   const double par2 = partner_of<ODD>(own2, lane_odd);
   const double alpha = lower ? own2 : par2;
   const double beta = lower ? par2 : own2;
@@ -296,6 +300,8 @@ __device__ __forceinline__ void jacobi_step(double (&g)[N], double (&v)[R], int 
       p = partner_of<ODD>(g[i], lane_odd);
     g[i] = fma(a_own, g[i], a_par * p);
   }
+  // ||a_own x + a_par y||^2 from the norms and the inner product
+  own2 = fma(a_own * a_own, own2, fma(a_par * a_par, par2, 2.0 * a_own * a_par * gam));
   if constexpr (ACCUM) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -318,10 +324,19 @@ __device__ __forceinline__ void jacobi_onesided(double (&g)[N], double (&v)[R], 
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (__ballot(!done) == 0ull) break;
     bool rot = false, big = false;
+    double own0 = 0.0, own1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (i & 1)
+        own1 = fma(g[i], g[i], own1);
+      else
+        own0 = fma(g[i], g[i], own0);
+    }
+    double own2 = own0 + own1;
 #pragma nounroll
     for (int step = 0; step < NC; step += 2) {
-      jacobi_step<R, N, false, ACCUM>(g, v, j, lane_odd, done, tol2, stop2, rot, big);
-      jacobi_step<R, N, true, ACCUM>(g, v, j, lane_odd, done, tol2, stop2, rot, big);
+      jacobi_step<R, N, false, ACCUM>(g, v, own2, j, lane_odd, done, tol2, stop2, rot, big);
+      jacobi_step<R, N, true, ACCUM>(g, v, own2, j, lane_odd, done, tol2, stop2, rot, big);
     }
     (void)rot;
     if ((__ballot(big) & gmask) == 0ull) done = true;

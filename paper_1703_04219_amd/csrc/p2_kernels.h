@@ -42,11 +42,15 @@ struct BatchView {
   int dynamic = 0;
   int warm = 0;                    // warm-started polar (every problem has its basis E);
                                    // plan_launch clears it for ranks built without it
-  int max_hot = 0;                 // LDS hot columns of the mode-2 launch (max over problems)
+  int max_hot = 0;                 // hot columns planned by the problems (max over them)
   int64_t maxK = 0, maxJ = 0;
+  int m2_blocks = 0;               // mode-2 blocks meant to share a CU (0 = 1)
+  int m2_threads = 0;              // in: requested mode-2 block size (0 = default); out: used
   // filled by plan_launch (needs the current device; nothing but launches
   // happen afterwards, so the run_* calls below may be captured in a graph)
   int grid_alpha = 0, grid_gamma = 0, grid_mode2 = 0;
+  int m2_hot = 0;                  // hot columns of the mode-2 launch (<= max_hot)
+  size_t m2_lds = 0;               // dynamic LDS of one mode-2 block
 };
 
 // Subjects per Procrustes / mode-3 tile step (subject groups of one

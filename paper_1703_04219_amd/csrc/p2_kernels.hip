@@ -389,7 +389,10 @@ constexpr int kMode2Threads = 1024;
 
 template <int R>
 struct Mode2Lds {
-  static constexpr int kPerGroup = R * R;  // E_k (floats)
+  static constexpr int kPerGroup = R * Geo<R>::LDV;  // E_k (floats), rows of stride LDV
+  // floats before the group buffers: the hot partial sums, rounded up so
+  // that E rows are 16-byte aligned
+  static constexpr int hot_floats(int hot) { return (hot * R + 3) & ~3; }
 };
 
 template <int R>
@@ -407,7 +410,7 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2(const ProbDesc* __restr
   const int gpb = (blockDim.x / kWave) * GPW;
   const int gslot = wave * GPW + (L.live ? L.grp : 0);
   float* shM2 = reinterpret_cast<float*>(p2_smem);  // up to max_hot x R
-  float* Es = shM2 + (size_t)max_hot * R + gslot * Mode2Lds<R>::kPerGroup;
+  float* Es = shM2 + Mode2Lds<R>::hot_floats(max_hot) + gslot * Mode2Lds<R>::kPerGroup;
   const int c = L.j;
   const bool real = c < R;
   const int cc = real ? c : 0;
@@ -433,15 +436,17 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2(const ProbDesc* __restr
       for (int64_t k = tile.k0 + gslot; k < tile.k1; k += gpb) {
         const Subj s = X.subj(k);
         {
-          // E(:, c) = w(c) F^T H(:, c), stored row-major E(p, c) = Es[p * R + c]
+          // E(:, c) = w(c) F^T H(:, c), stored row-major E(p, c) = Es[p * LDV + c];
+          // the padding columns (c >= R) hold zeros
           const float* Fk = F + (size_t)k * R * R;
-          const float wc = W[k * R + cc];
+          const float wc = real ? W[k * R + cc] : 0.f;
 #pragma unroll
           for (int p = 0; p < R; ++p) {
             float tt = 0.f;
 #pragma unroll
             for (int q = 0; q < R; ++q) tt = fmaf(Fk[p * R + q], hc[q], tt);
-            if (real) Es[p * R + c] = tt * wc;
+            Es[p * LDV + c] = tt * wc;
+            if (c + NC < LDV) Es[p * LDV + c + NC] = 0.f;
           }
         }
         wave_sync();
@@ -464,13 +469,21 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2(const ProbDesc* __restr
               a[4 * q + 3] = fmaf(x, v4.w, a[4 * q + 3]);
             }
           }
-          float d[R];
+          // D(i, :) = A(i, :) E, reading E rows as 16-byte LDS vectors
+          float d[LDV];
 #pragma unroll
-          for (int q = 0; q < R; ++q) d[q] = 0.f;
+          for (int q = 0; q < LDV; ++q) d[q] = 0.f;
 #pragma unroll
           for (int p = 0; p < R; ++p) {
+            const float4* e4 = reinterpret_cast<const float4*>(Es + p * LDV);
 #pragma unroll
-            for (int q = 0; q < R; ++q) d[q] = fmaf(a[p], Es[p * R + q], d[q]);
+            for (int q = 0; q < LDV / 4; ++q) {
+              const float4 e = e4[q];
+              d[4 * q + 0] = fmaf(a[p], e.x, d[4 * q + 0]);
+              d[4 * q + 1] = fmaf(a[p], e.y, d[4 * q + 1]);
+              d[4 * q + 2] = fmaf(a[p], e.z, d[4 * q + 2]);
+              d[4 * q + 3] = fmaf(a[p], e.w, d[4 * q + 3]);
+            }
           }
           for (int z = zs; z < ze; ++z) {
             const int j = X.colat(s, z);
@@ -1290,7 +1303,10 @@ template <int R> constexpr size_t gamma_lds() {
   return gamma_shared<R>() + (size_t)(gamma_threads<R>() / kWave) * Geo<R>::GPW * gamma_group<R>();
 }
 template <int R> size_t mode2_lds(int hot) {
-  return sizeof(float) * (size_t)hot * R + mode2_groups_bytes<R>();
+  return sizeof(float) * (size_t)Mode2Lds<R>::hot_floats(hot) + mode2_groups_bytes<R>();
+}
+template <int R> size_t mode2_groups_bytes_at(int threads) {
+  return (size_t)(threads / kWave) * Geo<R>::GPW * mode2_group<R>();
 }
 
 int device_cus() {
@@ -1349,8 +1365,24 @@ hipError_t plan_t(BatchView& b) {
                       &b.grid_gamma);
     if (e != hipSuccess) return e;
   }
-  return resident_grid(k_mode2<R>, mode2_threads<R>(), mode2_lds<R>(b.max_hot), b.nm2,
-                       &b.grid_mode2);
+  // mode 2: blocks of m2_threads (0 = the rank's default) with m2_blocks of
+  // them sharing a CU; each block's hot-column partial sums get what its
+  // share of the LDS leaves after the groups' E buffers
+  const int bpc = b.m2_blocks > 0 ? b.m2_blocks : 1;
+  const size_t budget = kLdsBudget / (size_t)bpc;
+  int threads = b.m2_threads > 0 ? b.m2_threads : mode2_threads<R>();
+  threads = threads / kWave * kWave;
+  if (threads > kMode2Threads) threads = kMode2Threads;
+  while (threads > kWave && mode2_groups_bytes_at<R>(threads) > budget / 2) threads -= kWave;
+  if (threads < kWave || mode2_groups_bytes_at<R>(threads) + 2048 > budget)
+    return hipErrorInvalidConfiguration;
+  int hot = (int)((budget - 2048 - mode2_groups_bytes_at<R>(threads)) / (sizeof(float) * R));
+  if (hot > b.max_hot) hot = b.max_hot;
+  b.m2_threads = threads;
+  b.m2_hot = hot;
+  b.m2_lds = sizeof(float) * (size_t)Mode2Lds<R>::hot_floats(hot) +
+             mode2_groups_bytes_at<R>(threads);
+  return resident_grid(k_mode2<R>, threads, b.m2_lds, b.nm2, &b.grid_mode2);
 }
 
 inline int* tickets_of(const BatchView& b, int kind) {
@@ -1393,14 +1425,13 @@ hipError_t gamma_t(const BatchView& b, int parity, int do_next, const PolarParam
 
 template <int R>
 hipError_t mode2_t(const BatchView& b, int parity, hipStream_t s) {
-  hipLaunchKernelGGL(k_mode2<R>, dim3(b.grid_mode2), dim3(mode2_threads<R>()),
-                     mode2_lds<R>(b.max_hot), s, b.desc, b.m2tiles, b.nm2,
-                     tickets_of(b, kTicketMode2), parity, b.max_hot);
+  hipLaunchKernelGGL(k_mode2<R>, dim3(b.grid_mode2), dim3(b.m2_threads), b.m2_lds, s, b.desc,
+                     b.m2tiles, b.nm2, tickets_of(b, kTicketMode2), parity, b.m2_hot);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || b.max_hot == 0) return e;
-  int rb = (b.max_hot * R + 255) / 256;
+  if (e != hipSuccess || b.m2_hot == 0) return e;
+  int rb = (b.m2_hot * R + 255) / 256;
   if (rb > 1024) rb = 1024;
-  hipLaunchKernelGGL(k_mode2_reduce<R>, dim3(rb, b.np), dim3(256), 0, s, b.desc, b.max_hot);
+  hipLaunchKernelGGL(k_mode2_reduce<R>, dim3(rb, b.np), dim3(256), 0, s, b.desc, b.m2_hot);
   return hipGetLastError();
 }
 
@@ -1481,7 +1512,7 @@ size_t launch_lds(int R, int kernel) {
     switch (kernel) {                                                                       \
       case 0: return alpha_shared<r>() + (size_t)(alpha_threads<r>() / kWave) * Geo<r>::GPW * alpha_group<r>(); \
       case 1: return gamma_shared<r>() + (size_t)(gamma_threads<r>() / kWave) * Geo<r>::GPW * gamma_group<r>(); \
-      case 2: return sizeof(float) * (size_t)max_hot_t<r>() * r + mode2_groups_bytes<r>();  \
+      case 2: return mode2_lds<r>(max_hot_t<r>());                                          \
       case 3: return proj_shared<r>() + (size_t)(proj_threads<r>() / kWave) * Geo<r>::GPW * proj_group<r>();    \
       case 4: return (size_t)(getq_threads<r>() / kWave) * Geo<r>::GPW * getq_group<r>();   \
       default: return 0;                                                                    \

@@ -90,7 +90,8 @@ def test_batch_equals_one_problem_at_a_time(sched):
 
 @pytest.mark.parametrize("sched", [
     dict(tile_rounds=1), dict(tile_rounds=16), dict(dynamic=1), dict(dynamic=1, tile_rounds=2),
-    dict(m2_tiles=8), dict(graph=1), dict(graph=1, dynamic=1), dict(warm_polar=1)])
+    dict(m2_tiles=8), dict(graph=1), dict(graph=1, dynamic=1), dict(warm_polar=1),
+    dict(m2_threads=512, m2_blocks=2), dict(m2_threads=256, m2_blocks=4, dynamic=1)])
 def test_schedules_agree(sched):
     X, R = gen_config(2, k_limit=6000)
     H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, 2, 1])
