@@ -168,7 +168,8 @@ __device__ __forceinline__ void gather_rows2(const XS& X, const Subj& s, int i0,
 }
 
 // Gram rows from an LDS chunk: lane c (< R) accumulates row c of A^T B in
-// FP64 (products of the FP32 values are exact in FP64).
+// FP64 (products of the FP32 values are exact in FP64).  For even R the rows
+// of B are read as 16-byte LDS vectors (rows start 16-byte aligned).
 template <int R>
 __device__ __forceinline__ void gram_accum(const double* A, const double* B, int n, int c,
                                            double (&row)[R]) {
@@ -176,8 +177,48 @@ __device__ __forceinline__ void gram_accum(const double* A, const double* B, int
 #pragma nounroll
   for (int ii = 0; ii < n; ++ii) {
     const double a = A[ii * R + cc];
+    if constexpr (R % 2 == 0) {
+      const double2* b = reinterpret_cast<const double2*>(B + ii * R);
 #pragma unroll
-    for (int l = 0; l < R; ++l) row[l] = fma(a, B[ii * R + l], row[l]);
+      for (int l = 0; l < R / 2; ++l) {
+        const double2 bb = b[l];
+        row[2 * l] = fma(a, bb.x, row[2 * l]);
+        row[2 * l + 1] = fma(a, bb.y, row[2 * l + 1]);
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < R; ++l) row[l] = fma(a, B[ii * R + l], row[l]);
+    }
+  }
+}
+
+// Rows c of A0^T A1 and A1^T A1 together (one read of each A1 row).
+template <int R>
+__device__ __forceinline__ void gram_accum2(const double* A0, const double* A1, int n, int c,
+                                            double (&prow)[R], double (&crow)[R]) {
+  const int cc = c < R ? c : 0;
+#pragma nounroll
+  for (int ii = 0; ii < n; ++ii) {
+    const double a0 = A0[ii * R + cc];
+    const double a1 = A1[ii * R + cc];
+    if constexpr (R % 2 == 0) {
+      const double2* b = reinterpret_cast<const double2*>(A1 + ii * R);
+#pragma unroll
+      for (int l = 0; l < R / 2; ++l) {
+        const double2 bb = b[l];
+        prow[2 * l] = fma(a0, bb.x, prow[2 * l]);
+        prow[2 * l + 1] = fma(a0, bb.y, prow[2 * l + 1]);
+        crow[2 * l] = fma(a1, bb.x, crow[2 * l]);
+        crow[2 * l + 1] = fma(a1, bb.y, crow[2 * l + 1]);
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < R; ++l) {
+        const double b = A1[ii * R + l];
+        prow[l] = fma(a0, b, prow[l]);
+        crow[l] = fma(a1, b, crow[l]);
+      }
+    }
   }
 }
 

@@ -68,6 +68,9 @@ extern __shared__ __align__(16) unsigned char p2_smem[];
 // Per-group LDS of the polar kernels (doubles): a region that holds the
 // gather chunks in the first phase and C, F, P and the Jacobi scratch later,
 // then w, a second R-vector and the eigenvalue slots.
+// LDS layout of the per-subject kernels.  For even R every region below
+// starts at an even number of doubles (16-byte aligned), which the vector
+// reads of gram_accum rely on.
 template <int R>
 struct PolarLds {
   static constexpr int NC = Geo<R>::NC;
@@ -76,6 +79,8 @@ struct PolarLds {
   static constexpr int kB = R * R + NC * R;
   static constexpr int kRegion = kA > kB ? kA : kB;
   static constexpr int kPerGroup = kRegion + 2 * R + NC;
+  static_assert(R % 2 == 1 || (kPerGroup % 2 == 0 && (CH * R) % 2 == 0),
+                "even-R group regions must stay 16-byte aligned");
 };
 
 template <int R>
@@ -289,8 +294,7 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
             const int n = min(CH, s.nrows - i0);
             gather_rows2<R>(X, s, i0, n, V0, V1, A0, A1, c);
             wave_sync();
-            gram_accum<R>(A0, A1, n, c, prow);  // row c of P = A^T A'
-            gram_accum<R>(A1, A1, n, c, crow);  // row c of C' = A'^T A'
+            gram_accum2<R>(A0, A1, n, c, prow, crow);  // rows c of P = A^T A', C' = A'^T A'
             wave_sync();
           }
           if (real) {
@@ -1269,6 +1273,9 @@ template <int R> constexpr int max_hot_t() {
 
 // every built rank has a launch configuration that fits the LDS
 #define P2_CHECK_PLAN(r)                                                         \
+  static_assert(r % 2 == 1 || (alpha_shared<r>() % 16 == 0 &&                    \
+                               gamma_shared<r>() % 16 == 0),                     \
+                "block LDS prefix must keep group regions 16-byte aligned");    \
   static_assert(alpha_threads<r>() > 0 && gamma_threads<r>() > 0 &&              \
                     proj_threads<r>() > 0 && getq_threads<r>() > 0 &&            \
                     mode2_threads<r>() > 0 && max_hot_t<r>() >= 0,               \
