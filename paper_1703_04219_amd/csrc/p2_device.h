@@ -26,6 +26,31 @@ struct Geo {
   static constexpr int CH = NC * ((24 + NC - 1) / NC);
 };
 
+// Global-memory views of pointers.  Buffers reached through descriptors in
+// memory are generic pointers to the compiler, which then emits FLAT
+// instructions; a FLAT access counts against the LDS wait counter as well, so
+// every LDS wait would also wait for the global loads and atomics in flight.
+// Casting to the global address space gives plain global instructions.
+#define P2_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ P2_GLOBAL T* glob(T* p) {
+  return (P2_GLOBAL T*)p;
+}
+
+// 16-byte global load (p 16-byte aligned)
+typedef float p2_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ p2_f4 ldg4(const float* p) {
+  return *reinterpret_cast<const P2_GLOBAL p2_f4*>(glob(p));
+}
+
+__device__ __forceinline__ void gadd(float* p, float v) {
+  __hip_atomic_fetch_add(glob(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gadd(double* p, double v) {
+  __hip_atomic_fetch_add(glob(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Orders LDS traffic between lanes of one wavefront (no workgroup barrier).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -54,18 +79,20 @@ struct XEnc {
   const float* val;
   __device__ __forceinline__ Subj subj(int64_t k) const {
     Subj s;
-    s.z0 = zbase[k];
-    s.r0 = rbase[k];
-    s.nrows = (int)(rbase[k + 1] - s.r0);
-    s.nnz = (int)(zbase[k + 1] - s.z0);
+    s.z0 = glob(zbase)[k];
+    s.r0 = glob(rbase)[k];
+    s.nrows = (int)(glob(rbase)[k + 1] - s.r0);
+    s.nnz = (int)(glob(zbase)[k + 1] - s.z0);
     return s;
   }
   __device__ __forceinline__ void row(const Subj& s, int i, int& zs, int& ze) const {
-    zs = rstart[s.r0 + i];
-    ze = (i + 1 < s.nrows) ? (int)rstart[s.r0 + i + 1] : s.nnz;
+    zs = glob(rstart)[s.r0 + i];
+    ze = (i + 1 < s.nrows) ? (int)glob(rstart)[s.r0 + i + 1] : s.nnz;
   }
-  __device__ __forceinline__ int colat(const Subj& s, int z) const { return col[s.z0 + z]; }
-  __device__ __forceinline__ float valat(const Subj& s, int z) const { return val[s.z0 + z]; }
+  __device__ __forceinline__ int colat(const Subj& s, int z) const { return glob(col)[s.z0 + z]; }
+  __device__ __forceinline__ float valat(const Subj& s, int z) const {
+    return glob(val)[s.z0 + z];
+  }
 };
 
 struct XRaw {
@@ -75,18 +102,20 @@ struct XRaw {
   const float* val;
   __device__ __forceinline__ Subj subj(int64_t k) const {
     Subj s;
-    s.r0 = subj_ptr[k];
-    s.nrows = (int)(subj_ptr[k + 1] - s.r0);
-    s.z0 = row_ptr[s.r0];
-    s.nnz = (int)(row_ptr[s.r0 + s.nrows] - s.z0);
+    s.r0 = glob(subj_ptr)[k];
+    s.nrows = (int)(glob(subj_ptr)[k + 1] - s.r0);
+    s.z0 = glob(row_ptr)[s.r0];
+    s.nnz = (int)(glob(row_ptr)[s.r0 + s.nrows] - s.z0);
     return s;
   }
   __device__ __forceinline__ void row(const Subj& s, int i, int& zs, int& ze) const {
-    zs = (int)(row_ptr[s.r0 + i] - s.z0);
-    ze = (int)(row_ptr[s.r0 + i + 1] - s.z0);
+    zs = (int)(glob(row_ptr)[s.r0 + i] - s.z0);
+    ze = (int)(glob(row_ptr)[s.r0 + i + 1] - s.z0);
   }
-  __device__ __forceinline__ int colat(const Subj& s, int z) const { return col[s.z0 + z]; }
-  __device__ __forceinline__ float valat(const Subj& s, int z) const { return val[s.z0 + z]; }
+  __device__ __forceinline__ int colat(const Subj& s, int z) const { return glob(col)[s.z0 + z]; }
+  __device__ __forceinline__ float valat(const Subj& s, int z) const {
+    return glob(val)[s.z0 + z];
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -110,10 +139,10 @@ __device__ __forceinline__ void gather_rows(const XS& X, const Subj& s, int i0, 
     for (int z = zs; z < ze; ++z) {
       const int col = X.colat(s, z);
       const float x = X.valat(s, z);
-      const float4* vr = reinterpret_cast<const float4*>(V + (size_t)col * LDV);
+      const float* vr = V + (size_t)col * LDV;
 #pragma unroll
       for (int q = 0; q < LDV / 4; ++q) {
-        const float4 t = vr[q];
+        const p2_f4 t = ldg4(vr + 4 * q);
         acc[4 * q + 0] = fmaf(x, t.x, acc[4 * q + 0]);
         acc[4 * q + 1] = fmaf(x, t.y, acc[4 * q + 1]);
         acc[4 * q + 2] = fmaf(x, t.z, acc[4 * q + 2]);
@@ -143,12 +172,12 @@ __device__ __forceinline__ void gather_rows2(const XS& X, const Subj& s, int i0,
     for (int z = zs; z < ze; ++z) {
       const int col = X.colat(s, z);
       const float x = X.valat(s, z);
-      const float4* v0 = reinterpret_cast<const float4*>(V0 + (size_t)col * LDV);
-      const float4* v1 = reinterpret_cast<const float4*>(V1 + (size_t)col * LDV);
+      const float* v0 = V0 + (size_t)col * LDV;
+      const float* v1 = V1 + (size_t)col * LDV;
 #pragma unroll
       for (int q = 0; q < LDV / 4; ++q) {
-        const float4 t = v0[q];
-        const float4 u = v1[q];
+        const p2_f4 t = ldg4(v0 + 4 * q);
+        const p2_f4 u = ldg4(v1 + 4 * q);
         a0[4 * q + 0] = fmaf(x, t.x, a0[4 * q + 0]);
         a0[4 * q + 1] = fmaf(x, t.y, a0[4 * q + 1]);
         a0[4 * q + 2] = fmaf(x, t.z, a0[4 * q + 2]);
@@ -421,7 +450,7 @@ __device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, con
   constexpr bool warm = WARM;
   double g[R], v[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = warm ? (double)E[c * R + i] : ((i == c) ? 1.0 : 0.0);
+  for (int i = 0; i < R; ++i) v[i] = warm ? (double)glob(E)[c * R + i] : ((i == c) ? 1.0 : 0.0);
   // T(c, :) = C(c, :) M^T,   T(c, j) = sum_l C(c, l) w(l) H(j, l)
   {
     double cw[R];
@@ -499,7 +528,7 @@ __device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, con
     wave_sync();
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      E[c * R + i] = (float)v[i];
+      glob(E)[c * R + i] = (float)v[i];
       S[c * R + i] = keep ? v[i] : 0.0;
     }
   } else {

@@ -58,7 +58,7 @@ __device__ __forceinline__ void block_reduce_atomic(double* sh, int n, double* o
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double v = sh[i];
-    if (v != 0.0) atomicAdd(out + i, v);
+    if (v != 0.0) gadd(out + i, v);
   }
 }
 
@@ -85,7 +85,7 @@ struct PolarLds {
 
 template <int R>
 __device__ __forceinline__ void load_shared_rxr(double* dst, const double* __restrict__ src) {
-  for (int i = threadIdx.x; i < R * R; i += blockDim.x) dst[i] = src[i];
+  for (int i = threadIdx.x; i < R * R; i += blockDim.x) dst[i] = glob(src)[i];
 }
 
 // M1 partial of one subject, column c: (Y_k V)(:, c) w(c)  (equation (mttkrp1_3))
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
           if (c < R) {
 #pragma unroll
             for (int l = 0; l < R; ++l) Cs[c * R + l] = crow[l];
-            wv[c] = (double)W[k * R + c];
+            wv[c] = (double)glob(W)[k * R + c];
           }
         }
         wave_sync();
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
                      pp.stop2,
                      pp.max_sweeps, f, y);
         if (c < R) {
-          float* Fk = F + (size_t)k * R * R + (size_t)c * R;
+          P2_GLOBAL float* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
           for (int q = 0; q < R; ++q) Fk[q] = (float)f[q];
           add_m1<R>(shM1, y, wv[c], c);
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
     double* M1 = D.small + SL.M1;
     for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
       const double v = shM1[q];
-      if (v != 0.0) atomicAdd(M1 + q, v);
+      if (v != 0.0) gadd(M1 + q, v);
     }
   }
 }
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
             wave_sync();
           }
           if (real) {
-            const float* Fk = F + (size_t)k * R * R + (size_t)c * R;
+            const P2_GLOBAL float* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
             for (int q = 0; q < R; ++q) SF[c * R + q] = (double)Fk[q];
 #pragma unroll
@@ -326,8 +326,8 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
 #pragma unroll
         for (int l = 0; l < R; ++l) wn = fma(mv[l], N3ps[l * R + cc], wn);
         if (real) {
-          W[k * R + c] = (float)wn;
-          M3[k * R + c] = (float)m3;
+          glob(W)[k * R + c] = (float)wn;
+          glob(M3)[k * R + c] = (float)m3;
           wv[c] = (double)(float)wn;
         }
         wave_sync();
@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
                        pp.stop2,
                        pp.max_sweeps, f, y);
           if (real) {
-            float* Fk = F + (size_t)k * R * R + (size_t)c * R;
+            P2_GLOBAL float* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
             for (int q = 0; q < R; ++q) Fk[q] = (float)f[q];
             add_m1<R>(shM1, y, wv[c], c);
@@ -369,12 +369,12 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
       double* M1 = D.small + SL.M1;
       for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
         const double v = shM1[q];
-        if (v != 0.0) atomicAdd(M1 + q, v);
+        if (v != 0.0) gadd(M1 + q, v);
       }
     }
     if (threadIdx.x == 0) {
-      atomicAdd(D.small + SL.fitacc + 0, shFit[0]);
-      atomicAdd(D.small + SL.fitacc + 1, shFit[1]);
+      gadd(D.small + SL.fitacc + 0, shFit[0]);
+      gadd(D.small + SL.fitacc + 1, shFit[1]);
     }
   }
 }
@@ -394,13 +394,18 @@ constexpr int kMode2Threads = 1024;
 template <int R>
 struct Mode2Lds {
   static constexpr int kPerGroup = R * Geo<R>::LDV;  // E_k (floats), rows of stride LDV
+  // largest workgroup; ranks above 20 use at most 512 threads so that a
+  // lane may hold 256 VGPRs
+  static constexpr int kMaxThreads = R <= 20 ? kMode2Threads : kMode2Threads / 2;
+  // rows a lane gathers per step (register budget: T x LDV floats)
+  static constexpr int kRowsPerStep = R <= 10 ? 4 : 2;
   // floats before the group buffers: the hot partial sums, rounded up so
   // that E rows are 16-byte aligned
   static constexpr int hot_floats(int hot) { return (hot * R + 3) & ~3; }
 };
 
 template <int R>
-__global__ void __launch_bounds__(kMode2Threads) k_mode2(const ProbDesc* __restrict__ P,
+__global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDesc* __restrict__ P,
                                                           const Tile* __restrict__ T, int ntiles,
                                                           int* tickets, int parity,
                                                           int max_hot) {
@@ -436,70 +441,118 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2(const ProbDesc* __restr
     if (L.live) {
       float hc[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) hc[q] = (float)D.H[q * R + cc];
+      for (int q = 0; q < R; ++q) hc[q] = (float)glob(D.H)[q * R + cc];
       for (int64_t k = tile.k0 + gslot; k < tile.k1; k += gpb) {
         const Subj s = X.subj(k);
         {
-          // E(:, c) = w(c) F^T H(:, c), stored row-major E(p, c) = Es[p * LDV + c];
-          // the padding columns (c >= R) hold zeros
-          const float* Fk = F + (size_t)k * R * R;
-          const float wc = real ? W[k * R + cc] : 0.f;
+          // F_k (R x R floats, F(q, p) at p * R + q) staged in the group's E
+          // buffer with coalesced loads, then E(:, c) = w(c) F^T H(:, c),
+          // stored row-major E(p, c) = Es[p * LDV + c]; the padding columns
+          // (c >= R) hold zeros
+          const P2_GLOBAL float* Fk = glob(F) + (size_t)k * R * R;
+          for (int f = c; f < R * R; f += NC) Es[f] = Fk[f];
+          const float wc = real ? glob(W)[k * R + cc] : 0.f;
+          wave_sync();
+          float e[R];
 #pragma unroll
           for (int p = 0; p < R; ++p) {
             float tt = 0.f;
 #pragma unroll
-            for (int q = 0; q < R; ++q) tt = fmaf(Fk[p * R + q], hc[q], tt);
-            Es[p * LDV + c] = tt * wc;
+            for (int q = 0; q < R; ++q) tt = fmaf(Es[p * R + q], hc[q], tt);
+            e[p] = tt * wc;
+          }
+          wave_sync();
+#pragma unroll
+          for (int p = 0; p < R; ++p) {
+            Es[p * LDV + c] = e[p];
             if (c + NC < LDV) Es[p * LDV + c + NC] = 0.f;
           }
         }
         wave_sync();
+        // T rows per lane and step: every row bound, first nonzero and V row
+        // of the step is requested before any of them is used, so a lane has
+        // T independent load chains in flight instead of one
+        constexpr int T = Mode2Lds<R>::kRowsPerStep;
+        const P2_GLOBAL uint16_t* __restrict__ rst = glob(X.rstart) + s.r0;
+        const P2_GLOBAL uint16_t* __restrict__ cl = glob(X.col) + s.z0;
+        const P2_GLOBAL float* __restrict__ vl = glob(X.val) + s.z0;
 #pragma nounroll
-        for (int ii = c; ii < s.nrows; ii += NC) {
-          int zs, ze;
-          X.row(s, ii, zs, ze);
-          float a[LDV];
+        for (int ib = 0; ib < s.nrows; ib += T * NC) {
+          int zs[T], ze[T];
 #pragma unroll
-          for (int q = 0; q < LDV; ++q) a[q] = 0.f;
-          for (int z = zs; z < ze; ++z) {
-            const float x = X.valat(s, z);
-            const float4* vr = reinterpret_cast<const float4*>(V + (size_t)X.colat(s, z) * LDV);
+          for (int t = 0; t < T; ++t) {
+            const int ii = ib + c + t * NC;
+            const bool ok = ii < s.nrows;
+            zs[t] = ok ? (int)rst[ii] : 0;
+            ze[t] = ok ? ((ii + 1 < s.nrows) ? (int)rst[ii + 1] : s.nnz) : 0;
+          }
+          int j0[T];
+          float x0[T];
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            const bool any = zs[t] < ze[t];
+            j0[t] = any ? (int)cl[zs[t]] : 0;
+            x0[t] = any ? vl[zs[t]] : 0.f;
+          }
+          float a[T][LDV];
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            const float* vr = V + (size_t)j0[t] * LDV;
 #pragma unroll
             for (int q = 0; q < LDV / 4; ++q) {
-              const float4 v4 = vr[q];
-              a[4 * q + 0] = fmaf(x, v4.x, a[4 * q + 0]);
-              a[4 * q + 1] = fmaf(x, v4.y, a[4 * q + 1]);
-              a[4 * q + 2] = fmaf(x, v4.z, a[4 * q + 2]);
-              a[4 * q + 3] = fmaf(x, v4.w, a[4 * q + 3]);
+              const p2_f4 v4 = ldg4(vr + 4 * q);
+              a[t][4 * q + 0] = x0[t] * v4.x;
+              a[t][4 * q + 1] = x0[t] * v4.y;
+              a[t][4 * q + 2] = x0[t] * v4.z;
+              a[t][4 * q + 3] = x0[t] * v4.w;
             }
           }
-          // D(i, :) = A(i, :) E, reading E rows as 16-byte LDS vectors
-          float d[LDV];
 #pragma unroll
-          for (int q = 0; q < LDV; ++q) d[q] = 0.f;
+          for (int t = 0; t < T; ++t) {
+            for (int z = zs[t] + 1; z < ze[t]; ++z) {
+              const float x = vl[z];
+              const float* vr = V + (size_t)cl[z] * LDV;
 #pragma unroll
-          for (int p = 0; p < R; ++p) {
-            const float4* e4 = reinterpret_cast<const float4*>(Es + p * LDV);
-#pragma unroll
-            for (int q = 0; q < LDV / 4; ++q) {
-              const float4 e = e4[q];
-              d[4 * q + 0] = fmaf(a[p], e.x, d[4 * q + 0]);
-              d[4 * q + 1] = fmaf(a[p], e.y, d[4 * q + 1]);
-              d[4 * q + 2] = fmaf(a[p], e.z, d[4 * q + 2]);
-              d[4 * q + 3] = fmaf(a[p], e.w, d[4 * q + 3]);
+              for (int q = 0; q < LDV / 4; ++q) {
+                const p2_f4 v4 = ldg4(vr + 4 * q);
+                a[t][4 * q + 0] = fmaf(x, v4.x, a[t][4 * q + 0]);
+                a[t][4 * q + 1] = fmaf(x, v4.y, a[t][4 * q + 1]);
+                a[t][4 * q + 2] = fmaf(x, v4.z, a[t][4 * q + 2]);
+                a[t][4 * q + 3] = fmaf(x, v4.w, a[t][4 * q + 3]);
+              }
             }
           }
-          for (int z = zs; z < ze; ++z) {
-            const int j = X.colat(s, z);
-            const float x = X.valat(s, z);
-            if (j < hot) {
-              float* dst = shM2 + j * R;
 #pragma unroll
-              for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
-            } else {
-              float* dst = M2 + (size_t)j * LDV;
+          for (int t = 0; t < T; ++t) {
+            if (zs[t] >= ze[t]) continue;
+            // D(i, :) = A(i, :) E, reading E rows as 16-byte LDS vectors
+            float d[LDV];
 #pragma unroll
-              for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
+            for (int q = 0; q < LDV; ++q) d[q] = 0.f;
+#pragma unroll
+            for (int p = 0; p < R; ++p) {
+              const float4* e4 = reinterpret_cast<const float4*>(Es + p * LDV);
+#pragma unroll
+              for (int q = 0; q < LDV / 4; ++q) {
+                const float4 e = e4[q];
+                d[4 * q + 0] = fmaf(a[t][p], e.x, d[4 * q + 0]);
+                d[4 * q + 1] = fmaf(a[t][p], e.y, d[4 * q + 1]);
+                d[4 * q + 2] = fmaf(a[t][p], e.z, d[4 * q + 2]);
+                d[4 * q + 3] = fmaf(a[t][p], e.w, d[4 * q + 3]);
+              }
+            }
+            for (int z = zs[t]; z < ze[t]; ++z) {
+              const int j = (z == zs[t]) ? j0[t] : (int)cl[z];
+              const float x = (z == zs[t]) ? x0[t] : vl[z];
+              if (j < hot) {
+                float* dst = shM2 + j * R;
+#pragma unroll
+                for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
+              } else {
+                float* dst = M2 + (size_t)j * LDV;
+#pragma unroll
+                for (int q = 0; q < R; ++q) gadd(dst + q, x * d[q]);
+              }
             }
           }
         }
@@ -507,7 +560,7 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2(const ProbDesc* __restr
       }
     }
     __syncthreads();
-    float* mine = D.part + (int64_t)tile.slot * hot * R;
+    P2_GLOBAL float* mine = glob(D.part) + (int64_t)tile.slot * hot * R;
     for (int q = threadIdx.x; q < hot * R; q += blockDim.x) mine[q] = shM2[q];
   }
 }
@@ -525,9 +578,9 @@ __global__ void __launch_bounds__(256) k_mode2_reduce(const ProbDesc* __restrict
   float* __restrict__ M2 = D.M2;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     float acc = 0.f;
-    for (int t = 0; t < D.nparts; ++t) acc += src[(int64_t)t * n + q];
+    for (int t = 0; t < D.nparts; ++t) acc += glob(src)[(int64_t)t * n + q];
     const int j = q / R, r = q - j * R;
-    M2[(size_t)j * LDV + r] += acc;
+    glob(M2)[(size_t)j * LDV + r] += acc;
   }
 }
 
@@ -554,7 +607,7 @@ __device__ void gram_rows(const float* __restrict__ A, int64_t n, int lda, doubl
     const int64_t gid = (int64_t)block * gpb + wave * GPW + L.grp;
     const int64_t stride = (int64_t)nblocks * gpb;
     for (int64_t r = gid; r < n; r += stride) {
-      const float* a = A + r * lda;
+      const P2_GLOBAL float* a = glob(A) + r * lda;
       const double ac = (double)a[c];
 #pragma unroll
       for (int l = 0; l < R; ++l) acc[l] = fma(ac, (double)a[l], acc[l]);
@@ -643,12 +696,12 @@ __global__ void __launch_bounds__(64) k_solve_h(const ProbDesc* __restrict__ P, 
   __shared__ double dl[NC];
   __shared__ double Hs[R * R];
   const ProbDesc& D = P[blockIdx.x];
-  const double* M1 = D.small + SL.M1;
-  const double* WtW = D.small + SL.WtW;
-  const double* VtV = D.small + SL.VtV;
-  double* HtH = D.small + SL.HtH;
-  double* N2p = D.small + SL.N2p;
-  double* H = D.H;
+  const P2_GLOBAL double* M1 = glob(D.small) + SL.M1;
+  const P2_GLOBAL double* WtW = glob(D.small) + SL.WtW;
+  const P2_GLOBAL double* VtV = glob(D.small) + SL.VtV;
+  P2_GLOBAL double* HtH = glob(D.small) + SL.HtH;
+  P2_GLOBAL double* N2p = glob(D.small) + SL.N2p;
+  P2_GLOBAL double* H = glob(D.H);
   const int c = threadIdx.x;
   const int cc = c < R ? c : 0;
   double ncol[R], np[R];
@@ -699,9 +752,9 @@ __global__ void __launch_bounds__(256) k_vupdate(const ProbDesc* __restrict__ P,
   constexpr int LDV = Geo<R>::LDV;
   constexpr SmallLayout SL = small_layout(R);
   const ProbDesc& D = P[blockIdx.y];
-  const float* M2 = D.M2;
-  const double* N2p = D.small + SL.N2p;
-  float* Vout = D.V[parity ^ 1];
+  const P2_GLOBAL float* M2 = glob(D.M2);
+  const P2_GLOBAL double* N2p = glob(D.small) + SL.N2p;
+  P2_GLOBAL float* Vout = glob(D.V[parity ^ 1]);
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < D.J;
        j += (int64_t)gridDim.x * blockDim.x) {
     double m[R];
@@ -727,12 +780,12 @@ __global__ void __launch_bounds__(64) k_solve_n3(const ProbDesc* __restrict__ P,
   __shared__ double dl[NC];
   __shared__ double inv[R];
   const ProbDesc& D = P[blockIdx.x];
-  const double* VtVraw = D.small + SL.VtVraw;
-  const double* HtH = D.small + SL.HtH;
-  double* VtV = D.small + SL.VtV;
-  double* invnorm = D.small + SL.inv;
-  double* N3 = D.small + SL.N3;
-  double* N3p = D.small + SL.N3p;
+  const P2_GLOBAL double* VtVraw = glob(D.small) + SL.VtVraw;
+  const P2_GLOBAL double* HtH = glob(D.small) + SL.HtH;
+  P2_GLOBAL double* VtV = glob(D.small) + SL.VtV;
+  P2_GLOBAL double* invnorm = glob(D.small) + SL.inv;
+  P2_GLOBAL double* N3 = glob(D.small) + SL.N3;
+  P2_GLOBAL double* N3p = glob(D.small) + SL.N3p;
   const int c = threadIdx.x;
   const int cc = c < R ? c : 0;
   if (c < R) {
@@ -764,8 +817,8 @@ __global__ void __launch_bounds__(256) k_vscale(const ProbDesc* __restrict__ P, 
   constexpr int LDV = Geo<R>::LDV;
   constexpr SmallLayout SL = small_layout(R);
   const ProbDesc& D = P[blockIdx.y];
-  float* Vv = D.V[parity ^ 1];
-  const double* invnorm = D.small + SL.inv;
+  P2_GLOBAL float* Vv = glob(D.V[parity ^ 1]);
+  const P2_GLOBAL double* invnorm = glob(D.small) + SL.inv;
   const int64_t n = D.J * LDV;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -784,16 +837,16 @@ __global__ void __launch_bounds__(256) k_zero(const ProbDesc* __restrict__ P, in
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nth = gridDim.x * blockDim.x;
   if (mask & 1)
-    for (int q = tid; q < R * R; q += nth) D.small[SL.M1 + q] = 0.0;
+    for (int q = tid; q < R * R; q += nth) glob(D.small)[SL.M1 + q] = 0.0;
   if (mask & 2)
-    for (int q = tid; q < R * R; q += nth) D.small[SL.WtW + q] = 0.0;
+    for (int q = tid; q < R * R; q += nth) glob(D.small)[SL.WtW + q] = 0.0;
   if (mask & 4)
-    for (int q = tid; q < R * R; q += nth) D.small[SL.VtVraw + q] = 0.0;
+    for (int q = tid; q < R * R; q += nth) glob(D.small)[SL.VtVraw + q] = 0.0;
   if (mask & 8)
-    for (int q = tid; q < 2; q += nth) D.small[SL.fitacc + q] = 0.0;
+    for (int q = tid; q < 2; q += nth) glob(D.small)[SL.fitacc + q] = 0.0;
   if (mask & 16) {
     const int64_t n = D.J * LDV;
-    for (int64_t q = tid; q < n; q += nth) D.M2[q] = 0.f;
+    for (int64_t q = tid; q < n; q += nth) glob(D.M2)[q] = 0.f;
   }
 }
 
@@ -804,12 +857,12 @@ __global__ void k_fit(const ProbDesc* __restrict__ P) {
   constexpr SmallLayout SL = small_layout(R);
   if (threadIdx.x == 0) {
     const ProbDesc& D = P[blockIdx.x];
-    const double* fa = D.small + SL.fitacc;
-    const double nx2 = D.small[SL.nx2];
+    const P2_GLOBAL double* fa = glob(D.small) + SL.fitacc;
+    const double nx2 = glob(D.small)[SL.nx2];
     const double loss = nx2 - 2.0 * fa[0] + fa[1];
-    const int64_t it = D.iter[0];
-    D.small[SL.fits + (int)(it % kFitRing)] = 1.0 - loss / nx2;
-    D.iter[0] = it + 1;
+    const int64_t it = glob(D.iter)[0];
+    glob(D.small)[SL.fits + (int)(it % kFitRing)] = 1.0 - loss / nx2;
+    glob(D.iter)[0] = it + 1;
   }
 }
 
@@ -1260,7 +1313,7 @@ template <int R> constexpr int getq_threads() {
 // mode 2: the per-group buffers may take at most half of the LDS, the hot
 // column partial sums take the rest
 template <int R> constexpr int mode2_threads() {
-  return pick_threads<R>(0, mode2_group<R>(), kLdsBudget / 2, kMode2Threads);
+  return pick_threads<R>(0, mode2_group<R>(), kLdsBudget / 2, Mode2Lds<R>::kMaxThreads);
 }
 template <int R> constexpr size_t mode2_groups_bytes() {
   return (size_t)(mode2_threads<R>() / kWave) * Geo<R>::GPW * mode2_group<R>();
@@ -1379,7 +1432,7 @@ hipError_t plan_t(BatchView& b) {
   const size_t budget = kLdsBudget / (size_t)bpc;
   int threads = b.m2_threads > 0 ? b.m2_threads : mode2_threads<R>();
   threads = threads / kWave * kWave;
-  if (threads > kMode2Threads) threads = kMode2Threads;
+  if (threads > Mode2Lds<R>::kMaxThreads) threads = Mode2Lds<R>::kMaxThreads;
   while (threads > kWave && mode2_groups_bytes_at<R>(threads) > budget / 2) threads -= kWave;
   if (threads < kWave || mode2_groups_bytes_at<R>(threads) + 2048 > budget)
     return hipErrorInvalidConfiguration;
