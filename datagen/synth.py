@@ -238,9 +238,11 @@ def gen_config(cfg: int, k_limit: Optional[int] = None) -> tuple[Slices, int]:
 
 
 def gen_init(J: int, K: int, R: int, seed) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """Default initial state: H0 = I_R, W0 = ones (K x R), V0 ~ U[0,1) (J x R)."""
+    """Default initial state: H0 = I_R, W0 = ones (K x R), V0 ~ U[0,1) (J x R).
+    V0 is rounded to float32 values (held in float64), so that a float32 copy
+    of it is exact."""
     rng = np.random.default_rng(np.random.SeedSequence(list(seed)))
-    V0 = rng.random((J, R))
+    V0 = rng.random((J, R)).astype(np.float32).astype(np.float64)
     return np.eye(R), V0, np.ones((K, R))
 
 

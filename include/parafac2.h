@@ -111,7 +111,7 @@ typedef struct {
   double tau_polar;  /* eigenvalues of G_k = B_k^T B_k (B_k = X_k V S_k H^T)
                         below tau_polar * lambda_max are dropped from the
                         inverse square root in the Procrustes step;
-                        0 -> 1e-10                                           */
+                        0 -> 1e-13                                           */
   double tau_pinv;   /* eigenvalue cut of the R x R pseudo-inverses of the
                         normal equations (Algorithm "CP-ALS"), relative to
                         lambda_max; 0 -> R * 2.22e-16                         */

@@ -43,7 +43,8 @@ struct ProbDesc {
   float* V[2];      // V_t / V_{t+1} ping-pong, internal column order, row stride LDV
   float* W;         // K x R
   double* H;        // R x R (the caller's buffer)
-  float* F;         // K x R x R, per subject F_k column-major
+  double* F;        // K x R x R, per subject F_k column-major (FP64: F carries the
+                    // 1/sigma_min scale of ill-conditioned subjects)
   float* M2;        // J x LDV
   float* M3;        // K x R
   float* E;         // K x NC x R eigenvector bases of G_k (warm start), or nullptr

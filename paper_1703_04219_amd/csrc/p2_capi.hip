@@ -117,7 +117,7 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const p
   p.hist = take(sizeof(uint32_t) * J);
   p.V[0] = take(sizeof(float) * J * LDV);
   p.V[1] = take(sizeof(float) * J * LDV);
-  p.F = take(sizeof(float) * (size_t)K * R * R);
+  p.F = take(sizeof(double) * (size_t)K * R * R);
   p.M2 = take(sizeof(float) * J * LDV);
   p.M3 = take(sizeof(float) * (size_t)K * R);
   p.warm = (o && o->keep_bases) && p2::warm_supported(R);
@@ -138,7 +138,10 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const p
 p2::PolarParams polar_params(const parafac2_opts* o, int R) {
   p2::PolarParams pp;
   const int NC = (R & 1) ? R + 1 : R;
-  pp.tau_polar = (o && o->tau_polar > 0) ? o->tau_polar : 1e-10;
+  // eigenvalues of G that should be zero (exact rank deficiency of X_k)
+  // come out below ~1e-15 lambda_max from FP32-accumulated A_k, while genuine
+  // ones reach ~1e-11 lambda_max on the Zipf workloads: cut in between
+  pp.tau_polar = (o && o->tau_polar > 0) ? o->tau_polar : 1e-13;
   pp.tau_pinv = (o && o->tau_pinv > 0) ? o->tau_pinv : R * 2.220446049250313e-16;
   pp.tol = 8.0 * 2.220446049250313e-16 * std::sqrt((double)NC);
   pp.tau_c = 1e-12;
@@ -214,7 +217,7 @@ struct parafac2_ctx {
     d.V[1] = V(1);
     d.W = W;
     d.H = H;
-    d.F = at<float>(plan.F);
+    d.F = at<double>(plan.F);
     d.M2 = at<float>(plan.M2);
     d.M3 = at<float>(plan.M3);
     d.E = plan.warm ? at<float>(plan.E) : nullptr;
@@ -990,7 +993,7 @@ int parafac2_get_q(parafac2_ctx* c, int64_t k0, int64_t k1, float* Q) {
   if (c->have_F || c->qv < 0)
     return fail(P2_ESTATE, "no completed Procrustes step to report");
   if (k0 == k1) return P2_OK;
-  HIP_TRY(p2::run_getq(c->R, c->X, k0, k1, c->V(c->qv), c->at<float>(c->plan.F), Q,
+  HIP_TRY(p2::run_getq(c->R, c->X, k0, k1, c->V(c->qv), c->at<double>(c->plan.F), Q,
                        c->subj_host[k0], c->stream));
   return P2_OK;
 }

@@ -58,6 +58,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Makes v count as computed (and redefined) at this point: the scheduler may
+// otherwise sink the arithmetic that produces v past a following barrier, or
+// hoist a conversion of v out of a loop, and keep the wider values live.
+// Emits no instruction.
+__device__ __forceinline__ void settle(double& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void settle(float& v) { asm volatile("" : "+v"(v)); }
+
 // ---------------------------------------------------------------------------
 // Slice access.  XEnc is the re-encoded collection built at init (16-bit
 // columns relabelled by frequency, 16-bit row starts relative to the subject),

@@ -76,7 +76,7 @@ hipError_t run_zero(const BatchView& b, int mask, hipStream_t s);
 hipError_t run_fit(const BatchView& b, hipStream_t s);
 hipError_t run_reset_tickets(const BatchView& b, hipStream_t s);
 hipError_t run_gram_rows(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s);
-hipError_t run_getq(int R, const XEnc& X, int64_t k0, int64_t k1, const float* V, const float* F,
+hipError_t run_getq(int R, const XEnc& X, int64_t k0, int64_t k1, const float* V, const double* F,
                     float* Q, int64_t row0, hipStream_t s);
 hipError_t run_project(int R, const XRaw& X, int64_t K, const float* V, const double* H,
                        const double* N3, const double* N3p, int n_steps, const float* w0,

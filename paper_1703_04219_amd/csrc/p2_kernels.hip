@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
     const XEnc X = D.X;
     const float* __restrict__ V = D.V[parity];
     const float* __restrict__ W = D.W;
-    float* __restrict__ F = D.F;
+    double* __restrict__ F = D.F;
     __syncthreads();
     load_shared_rxr<R>(Hs, D.H);
     for (int q = threadIdx.x; q < R * R; q += blockDim.x) shM1[q] = 0.0;
@@ -207,9 +207,9 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
                      pp.stop2,
                      pp.max_sweeps, f, y);
         if (c < R) {
-          P2_GLOBAL float* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
+          P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
-          for (int q = 0; q < R; ++q) Fk[q] = (float)f[q];
+          for (int q = 0; q < R; ++q) Fk[q] = f[q];
           add_m1<R>(shM1, y, wv[c], c);
         }
         wave_sync();
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
     const float* __restrict__ V0 = D.V[parity];
     const float* __restrict__ V1 = D.V[parity ^ 1];
     float* __restrict__ W = D.W;
-    float* __restrict__ F = D.F;
+    double* __restrict__ F = D.F;
     float* __restrict__ M3 = D.M3;
     __syncthreads();
     load_shared_rxr<R>(Hs, D.H);
@@ -298,9 +298,9 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
             wave_sync();
           }
           if (real) {
-            const P2_GLOBAL float* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
+            const P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
-            for (int q = 0; q < R; ++q) SF[c * R + q] = (double)Fk[q];
+            for (int q = 0; q < R; ++q) SF[c * R + q] = Fk[q];
 #pragma unroll
             for (int l = 0; l < R; ++l) SP[c * R + l] = prow[l];
           }
@@ -351,9 +351,9 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
                        pp.stop2,
                        pp.max_sweeps, f, y);
           if (real) {
-            P2_GLOBAL float* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
+            P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
-            for (int q = 0; q < R; ++q) Fk[q] = (float)f[q];
+            for (int q = 0; q < R; ++q) Fk[q] = f[q];
             add_m1<R>(shM1, y, wv[c], c);
           }
         }
@@ -393,12 +393,15 @@ constexpr int kMode2Threads = 1024;
 
 template <int R>
 struct Mode2Lds {
-  static constexpr int kPerGroup = R * Geo<R>::LDV;  // E_k (floats), rows of stride LDV
-  // largest workgroup; ranks above 20 use at most 512 threads so that a
-  // lane may hold 256 VGPRs
-  static constexpr int kMaxThreads = R <= 20 ? kMode2Threads : kMode2Threads / 2;
+  // E_k in FP64, rows of stride LDV, counted in floats: E_k = F^T H' diag(w')
+  // carries the 1/sigma_min scale of ill-conditioned subjects, so D = A E_k
+  // cancels and is formed in FP64
+  static constexpr int kPerGroup = 2 * R * Geo<R>::LDV;
+  // largest workgroup; ranks above 16 use at most 512 threads so that a
+  // lane may hold 256 VGPRs (the FP64 D row alone takes 2R of them)
+  static constexpr int kMaxThreads = R <= 16 ? kMode2Threads : kMode2Threads / 2;
   // rows a lane gathers per step (register budget: T x LDV floats)
-  static constexpr int kRowsPerStep = R <= 10 ? 4 : 2;
+  static constexpr int kRowsPerStep = R <= 6 ? 4 : (R <= 10 ? 3 : 2);
   // floats before the group buffers: the hot partial sums, rounded up so
   // that E rows are 16-byte aligned
   static constexpr int hot_floats(int hot) { return (hot * R + 3) & ~3; }
@@ -419,7 +422,8 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
   const int gpb = (blockDim.x / kWave) * GPW;
   const int gslot = wave * GPW + (L.live ? L.grp : 0);
   float* shM2 = reinterpret_cast<float*>(p2_smem);  // up to max_hot x R
-  float* Es = shM2 + Mode2Lds<R>::hot_floats(max_hot) + gslot * Mode2Lds<R>::kPerGroup;
+  double* Es = reinterpret_cast<double*>(shM2 + Mode2Lds<R>::hot_floats(max_hot) +
+                                         gslot * Mode2Lds<R>::kPerGroup);
   const int c = L.j;
   const bool real = c < R;
   const int cc = real ? c : 0;
@@ -432,13 +436,17 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
     const XEnc X = D.X;
     const float* __restrict__ V = D.V[parity];
     const float* __restrict__ W = D.W;
-    const float* __restrict__ F = D.F;
+    const double* __restrict__ F = D.F;
     float* __restrict__ M2 = D.M2;
     const int hot = min(D.hot, max_hot);
     __syncthreads();
     for (int q = threadIdx.x; q < hot * R; q += blockDim.x) shM2[q] = 0.f;
     __syncthreads();
     if (L.live) {
+      // H'(:, c) held as FP32: with E = F^T H' diag(w') formed in FP64, a
+      // rounding dH of H' moves D = A E by Q_k dH diag(w'), and Q_k = A F^T
+      // has orthonormal columns, so that change is not scaled by the
+      // condition number of the subject as a rounding of E would be
       float hc[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) hc[q] = (float)glob(D.H)[q * R + cc];
@@ -449,23 +457,26 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
           // buffer with coalesced loads, then E(:, c) = w(c) F^T H(:, c),
           // stored row-major E(p, c) = Es[p * LDV + c]; the padding columns
           // (c >= R) hold zeros
-          const P2_GLOBAL float* Fk = glob(F) + (size_t)k * R * R;
+          const P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R;
           for (int f = c; f < R * R; f += NC) Es[f] = Fk[f];
-          const float wc = real ? glob(W)[k * R + cc] : 0.f;
+          const double wc = real ? (double)glob(W)[k * R + cc] : 0.0;
+#pragma unroll
+          for (int q = 0; q < R; ++q) settle(hc[q]);  // widened here, per subject
           wave_sync();
-          float e[R];
+          double e[R];
 #pragma unroll
           for (int p = 0; p < R; ++p) {
-            float tt = 0.f;
+            double tt = 0.0;
 #pragma unroll
-            for (int q = 0; q < R; ++q) tt = fmaf(Es[p * R + q], hc[q], tt);
+            for (int q = 0; q < R; ++q) tt = fma(Es[p * R + q], (double)hc[q], tt);
             e[p] = tt * wc;
+            settle(e[p]);
           }
           wave_sync();
 #pragma unroll
           for (int p = 0; p < R; ++p) {
             Es[p * LDV + c] = e[p];
-            if (c + NC < LDV) Es[p * LDV + c + NC] = 0.f;
+            if (c + NC < LDV) Es[p * LDV + c + NC] = 0.0;
           }
         }
         wave_sync();
@@ -525,20 +536,20 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
 #pragma unroll
           for (int t = 0; t < T; ++t) {
             if (zs[t] >= ze[t]) continue;
-            // D(i, :) = A(i, :) E, reading E rows as 16-byte LDS vectors
-            float d[LDV];
+            // D(i, :) = A(i, :) E in FP64, reading E rows as 16-byte LDS vectors
+            // (NC columns: the padding of E beyond them is never read)
+            double d[NC];
 #pragma unroll
-            for (int q = 0; q < LDV; ++q) d[q] = 0.f;
+            for (int q = 0; q < NC; ++q) d[q] = 0.0;
 #pragma unroll
             for (int p = 0; p < R; ++p) {
-              const float4* e4 = reinterpret_cast<const float4*>(Es + p * LDV);
+              const double ap = (double)a[t][p];
+              const double2* e2 = reinterpret_cast<const double2*>(Es + p * LDV);
 #pragma unroll
-              for (int q = 0; q < LDV / 4; ++q) {
-                const float4 e = e4[q];
-                d[4 * q + 0] = fmaf(a[t][p], e.x, d[4 * q + 0]);
-                d[4 * q + 1] = fmaf(a[t][p], e.y, d[4 * q + 1]);
-                d[4 * q + 2] = fmaf(a[t][p], e.z, d[4 * q + 2]);
-                d[4 * q + 3] = fmaf(a[t][p], e.w, d[4 * q + 3]);
+              for (int q = 0; q < NC / 2; ++q) {
+                const double2 e = e2[q];
+                d[2 * q + 0] = fma(ap, e.x, d[2 * q + 0]);
+                d[2 * q + 1] = fma(ap, e.y, d[2 * q + 1]);
               }
             }
             for (int z = zs[t]; z < ze[t]; ++z) {
@@ -547,11 +558,11 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
               if (j < hot) {
                 float* dst = shM2 + j * R;
 #pragma unroll
-                for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * d[q]);
+                for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * (float)d[q]);
               } else {
                 float* dst = M2 + (size_t)j * LDV;
 #pragma unroll
-                for (int q = 0; q < R; ++q) gadd(dst + q, x * d[q]);
+                for (int q = 0; q < R; ++q) gadd(dst + q, x * (float)d[q]);
               }
             }
           }
@@ -876,7 +887,7 @@ __global__ void k_fill_i32(int* __restrict__ p, int n, int v) {
 template <int R>
 __global__ void __launch_bounds__(256) k_getq(XEnc X, int64_t k0, int64_t k1,
                                                const float* __restrict__ V,
-                                               const float* __restrict__ F, float* __restrict__ Q,
+                                               const double* __restrict__ F, float* __restrict__ Q,
                                                int64_t row0) {
   constexpr int NC = Geo<R>::NC;
   constexpr int GPW = Geo<R>::GPW;
@@ -891,8 +902,8 @@ __global__ void __launch_bounds__(256) k_getq(XEnc X, int64_t k0, int64_t k1,
   const int64_t stride = (int64_t)gridDim.x * groups_per_block;
   for (int64_t k = k0 + gid; k < k1; k += stride) {
     const Subj s = X.subj(k);
-    float fr[R];  // row c of F^T = column c of F ... Q(i, c) = sum_p A(i, p) F(c, p)
-    const float* Fk = F + (size_t)k * R * R;
+    double fr[R];  // Q(i, c) = sum_p A(i, p) F(c, p), F(c, p) at p R + c
+    const P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R;
     const int cc = c < R ? c : 0;
 #pragma unroll
     for (int p = 0; p < R; ++p) fr[p] = Fk[p * R + cc];
@@ -902,10 +913,10 @@ __global__ void __launch_bounds__(256) k_getq(XEnc X, int64_t k0, int64_t k1,
       wave_sync();
       if (c < R) {
         for (int ii = 0; ii < n; ++ii) {
-          float t = 0.f;
+          double t = 0.0;
 #pragma unroll
-          for (int p = 0; p < R; ++p) t = fmaf(gbuf[ii * R + p], fr[p], t);
-          Q[(s.r0 - row0 + i0 + ii) * R + c] = t;
+          for (int p = 0; p < R; ++p) t = fma((double)gbuf[ii * R + p], fr[p], t);
+          Q[(s.r0 - row0 + i0 + ii) * R + c] = (float)t;
         }
       }
       wave_sync();
@@ -1505,7 +1516,7 @@ hipError_t gram_t(const BatchView& b, int which, int parity, hipStream_t s) {
 }
 
 template <int R>
-hipError_t getq_t(const XEnc& X, int64_t k0, int64_t k1, const float* V, const float* F, float* Q,
+hipError_t getq_t(const XEnc& X, int64_t k0, int64_t k1, const float* V, const double* F, float* Q,
                   int64_t row0, hipStream_t s) {
   constexpr int T = getq_threads<R>();
   const int gpb = (T / kWave) * Geo<R>::GPW;
@@ -1603,7 +1614,7 @@ int launch_threads(int R, int kernel) {
   }
 }
 
-hipError_t run_getq(int R, const XEnc& X, int64_t k0, int64_t k1, const float* V, const float* F,
+hipError_t run_getq(int R, const XEnc& X, int64_t k0, int64_t k1, const float* V, const double* F,
                     float* Q, int64_t row0, hipStream_t s) {
   P2_DISPATCH(R, return getq_t<RR>(X, k0, k1, V, F, Q, row0, s))
 }

@@ -94,16 +94,18 @@ def test_launch_plans_fit_the_lds(R):
 @pytest.mark.parametrize("R", B.SUPPORTED_R)
 def test_workspace_size_is_sane(R):
     # K=1e6, J=5000, 55M rows, 63M nnz: encoded slices ~0.5 GB plus
-    # K*R*R*4 bytes of F per subject and, for the ranks with warm-started
+    # K*R*R*8 bytes of F per subject and, for the ranks with warm-started
     # eigen-solves, K*NC*R*4 bytes of kept bases; never wrapped around
     base = 63_000_000 * 6 + 55_000_000 * 2
     n = B.parafac2_workspace_size(1_000_000, 5000, 55_000_000, 63_000_000, R)
-    assert base + 1_000_000 * R * R * 4 <= n <= base + 1_000_000 * R * R * 4 + 2e9
+    f = R * R * 8  # F_k in FP64
+    assert base + 1_000_000 * f <= n <= base + 1_000_000 * f + 2e9
     nc = R + (R & 1)
-    per_subject = R * R * 4 + (nc * R * 4 if R <= 20 else 0)
+    per_subject = f + (nc * R * 4 if R <= 20 else 0)
     kept = B.parafac2_workspace_size(1_000_000, 5000, 55_000_000, 63_000_000, R,
                                      B.make_opts(keep_bases=True))
     assert base + 1_000_000 * per_subject <= kept <= base + 1_000_000 * per_subject + 2e9
+    assert base + 1_000_000 * f <= n
     small = B.parafac2_workspace_size(10, 50, 100, 300, R)
     assert 0 < small < 64 * 2**20
 

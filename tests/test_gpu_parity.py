@@ -91,6 +91,51 @@ def test_other_ranks_one_iteration(R):
     _compare_one_iteration(X, R, H0, V0, W0)
 
 
+def _with_empty_rows(X, every=3):
+    """X with an empty row inserted after every `every`-th row of each subject
+    (empty rows are accepted and contribute nothing)."""
+    from datagen.synth import Slices
+    rp, sp = [0], [0]
+    for k in range(X.K):
+        r0, r1 = int(X.subj_ptr[k]), int(X.subj_ptr[k + 1])
+        n = 0
+        for i in range(r0, r1):
+            rp.append(int(X.row_ptr[i + 1]))
+            n += 1
+            if (i - r0) % every == every - 1:
+                rp.append(rp[-1])
+                n += 1
+        sp.append(sp[-1] + n)
+    return Slices(X.J, np.array(sp, np.int64), np.array(rp, np.int64), X.col.copy(), X.val.copy())
+
+
+def test_edge_empty_rows():
+    X, R = gen_config(1)
+    Xe = _with_empty_rows(X)
+    assert Xe.n_rows > X.n_rows and Xe.nnz == X.nnz
+    H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, 1, 1])
+    _compare_one_iteration(Xe, R, H0, V0, W0)
+
+
+def test_edge_single_subject_and_minimal_rows():
+    # one subject; and every subject with exactly I_k = R rows
+    X = gen_slices(1, 40, (30, 30), _poisson_plus_one(3.0), "uniform", [4242])
+    H0, V0, W0 = gen_init(X.J, X.K, 5, [4242, 1])
+    _compare_one_iteration(X, 5, H0, V0, W0)
+    X = gen_slices(500, 60, (4, 4), _poisson_plus_one(3.0), "uniform", [4343])
+    H0, V0, W0 = gen_init(X.J, X.K, 4, [4343, 1])
+    _compare_one_iteration(X, 4, H0, V0, W0)
+
+
+@pytest.mark.parametrize("K", [7, 97, 1001])
+def test_edge_ragged_subject_counts(K):
+    # subject counts that leave partial tiles, partial bins and idle blocks
+    # (a single subject is covered by test_edge_single_subject_and_minimal_rows)
+    X = gen_slices(K, 80, (6, 20), _poisson_plus_one(2.0), "zipf", [5000 + K])
+    H0, V0, W0 = gen_init(X.J, X.K, 6, [5000 + K, 1])
+    _compare_one_iteration(X, 6, H0, V0, W0)
+
+
 def test_get_q_matches_oracle_and_is_orthonormal():
     X, R = gen_config(1)
     H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, 1, 1])
