@@ -35,8 +35,9 @@ def parse():
     p.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
                    help="1-3 one decomposition; 4 the 64-problem batch; 5 the serving trace")
     p.add_argument("--k-limit", type=int, default=None, help="only the first K subjects")
-    p.add_argument("--cpu-subjects", type=int, default=30000,
-                   help="subjects in the oracle's timed sample (0 = skip)")
+    p.add_argument("--cpu-subjects", type=int, default=-1,
+                   help="subjects in the oracle's timed sample (0 = skip; default: about 12 s "
+                        "of oracle work, 60,000 subjects at R=10 and 6,000 at R=40)")
     p.add_argument("--profile-only", action="store_true",
                    help="skip the CPU baseline (for profiler runs)")
     p.add_argument("--no-autotune", action="store_true",
@@ -81,7 +82,7 @@ def stream_bytes(X, R: int) -> dict:
     per-subject state, as used by the per-iteration kernels."""
     K, n_rows, nnz = X.K, X.n_rows, X.nnz
     x = nnz * (2 + 4) + n_rows * 2 + (K + 1) * 16  # col16 + val, row starts, offsets
-    f = K * R * R * 4                              # F_k (float32 R x R)
+    f = K * R * R * 8                              # F_k (float64 R x R)
     w = K * R * 4
     return {"x": x, "f": f, "w": w}
 
@@ -359,7 +360,8 @@ def main():
     cpu = None
     if a.cpu_subjects and not a.profile_only:
         print("[bench] timing the oracle on a sample ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(a.config, min(a.cpu_subjects, X.K))
+        n_cpu = a.cpu_subjects if a.cpu_subjects > 0 else {1: X.K, 2: 60000, 3: 6000}[a.config]
+        cpu = cpu_baseline(a.config, min(n_cpu, X.K))
 
     name = CONFIGS[a.config]["name"] + ("" if a.k_limit is None else f"_first{X.K}")
     out = {
