@@ -393,10 +393,11 @@ constexpr int kMode2Threads = 1024;
 
 template <int R>
 struct Mode2Lds {
-  // E_k in FP64, rows of stride LDV, counted in floats: E_k = F^T H' diag(w')
-  // carries the 1/sigma_min scale of ill-conditioned subjects, so D = A E_k
-  // cancels and is formed in FP64
-  static constexpr int kPerGroup = 2 * R * Geo<R>::LDV;
+  // E_k in FP64, rows of stride NC (R rounded up to even, so that rows are
+  // 16-byte aligned), counted in floats: E_k = F^T H' diag(w') carries the
+  // 1/sigma_min scale of ill-conditioned subjects, so D = A E_k cancels and
+  // is formed in FP64
+  static constexpr int kPerGroup = 2 * R * Geo<R>::NC;
   // largest workgroup; ranks above 16 use at most 512 threads so that a
   // lane may hold 256 VGPRs (the FP64 D row alone takes 2R of them)
   static constexpr int kMaxThreads = R <= 16 ? kMode2Threads : kMode2Threads / 2;
@@ -453,10 +454,10 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
       for (int64_t k = tile.k0 + gslot; k < tile.k1; k += gpb) {
         const Subj s = X.subj(k);
         {
-          // F_k (R x R floats, F(q, p) at p * R + q) staged in the group's E
+          // F_k (R x R doubles, F(q, p) at p * R + q) staged in the group's E
           // buffer with coalesced loads, then E(:, c) = w(c) F^T H(:, c),
-          // stored row-major E(p, c) = Es[p * LDV + c]; the padding columns
-          // (c >= R) hold zeros
+          // stored row-major E(p, c) = Es[p * NC + c]; the padding column of
+          // an odd rank (c = R) holds zeros
           const P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R;
           for (int f = c; f < R * R; f += NC) Es[f] = Fk[f];
           const double wc = real ? (double)glob(W)[k * R + cc] : 0.0;
@@ -474,10 +475,7 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
           }
           wave_sync();
 #pragma unroll
-          for (int p = 0; p < R; ++p) {
-            Es[p * LDV + c] = e[p];
-            if (c + NC < LDV) Es[p * LDV + c + NC] = 0.0;
-          }
+          for (int p = 0; p < R; ++p) Es[p * NC + c] = e[p];
         }
         wave_sync();
         // T rows per lane and step: every row bound, first nonzero and V row
@@ -544,7 +542,7 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
 #pragma unroll
             for (int p = 0; p < R; ++p) {
               const double ap = (double)a[t][p];
-              const double2* e2 = reinterpret_cast<const double2*>(Es + p * LDV);
+              const double2* e2 = reinterpret_cast<const double2*>(Es + p * NC);
 #pragma unroll
               for (int q = 0; q < NC / 2; ++q) {
                 const double2 e = e2[q];
