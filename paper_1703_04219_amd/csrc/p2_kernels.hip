@@ -402,7 +402,7 @@ struct Mode2Lds {
   // lane may hold 256 VGPRs (the FP64 D row alone takes 2R of them)
   static constexpr int kMaxThreads = R <= 16 ? kMode2Threads : kMode2Threads / 2;
   // rows a lane gathers per step (register budget: T x LDV floats)
-  static constexpr int kRowsPerStep = R <= 6 ? 4 : (R <= 10 ? 3 : 2);
+  static constexpr int kRowsPerStep = R <= 6 ? 4 : (R <= 10 ? 3 : (R <= 20 ? 2 : 1));
   // floats before the group buffers: the hot partial sums, rounded up so
   // that E rows are 16-byte aligned
   static constexpr int hot_floats(int hot) { return (hot * R + 3) & ~3; }
@@ -464,14 +464,26 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
 #pragma unroll
           for (int q = 0; q < R; ++q) settle(hc[q]);  // widened here, per subject
           wave_sync();
+          // two rows of E at a time, each as two independent FMA chains; the
+          // settle after each pair keeps the scheduler from holding all of
+          // F_k in registers across the barrier below
           double e[R];
 #pragma unroll
-          for (int p = 0; p < R; ++p) {
-            double tt = 0.0;
+          for (int p0 = 0; p0 < R; p0 += 2) {
 #pragma unroll
-            for (int q = 0; q < R; ++q) tt = fma(Es[p * R + q], (double)hc[q], tt);
-            e[p] = tt * wc;
-            settle(e[p]);
+            for (int p = p0; p < p0 + 2 && p < R; ++p) {
+              double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+              for (int q = 0; q < R; ++q) {
+                if (q & 1)
+                  t1 = fma(Es[p * R + q], (double)hc[q], t1);
+                else
+                  t0 = fma(Es[p * R + q], (double)hc[q], t0);
+              }
+              e[p] = (t0 + t1) * wc;
+            }
+#pragma unroll
+            for (int p = p0; p < p0 + 2 && p < R; ++p) settle(e[p]);
           }
           wave_sync();
 #pragma unroll
