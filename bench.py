@@ -50,6 +50,25 @@ def parse():
     return p.parse_args()
 
 
+def copy_rate_gbps(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Achievable HBM rate on this device: a plain device-to-device copy of
+    nbytes, timed with events (read + write bytes over the best launch)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
 def copy_calibration(nbytes: int):
     import torch
     n = nbytes // 4
@@ -85,6 +104,20 @@ def stream_bytes(X, R: int) -> dict:
     f = K * R * R * 8                              # F_k (float64 R x R)
     w = K * R * 4
     return {"x": x, "f": f, "w": w}
+
+
+def algorithmic_bytes(X, R: int) -> dict:
+    """Algorithmic HBM bytes of one launch of each per-iteration kernel."""
+    sb = stream_bytes(X, R)
+    LDV = (R + 3) & ~3
+    v_bytes = X.J * LDV * 4
+    return {
+        # k_gamma: X once, F read + F write (next Procrustes step), W and M3 written, V_t, V_{t+1}
+        "gamma": sb["x"] + 2 * sb["f"] + 2 * sb["w"] + 2 * v_bytes,
+        # k_mode2: X once, F and W read, V_t, M2 written
+        "mode2": sb["x"] + sb["f"] + sb["w"] + 2 * v_bytes,
+        "alpha": sb["x"] + sb["f"] + sb["w"] + v_bytes,
+    }
 
 
 def cpu_baseline(cfg: int, n_subjects: int):
@@ -302,6 +335,12 @@ def main():
     ctx = B.Context(dX, R, H0, V0, W0)
     del dX  # the context re-encoded the input into its workspace
     torch.cuda.synchronize()
+    # device memory held from here on: the workspace (re-encoded X, per-subject
+    # state, partial sums) and the factors; the peak includes the input copy
+    # that init reads
+    footprint = {"steady_bytes": int(torch.cuda.memory_allocated()),
+                 "peak_bytes": int(torch.cuda.max_memory_allocated()),
+                 "workspace_bytes": int(ctx.ws_bytes)}
     print(f"[bench] init done, workspace {ctx.ws_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
     chosen, tuned_ms = None, None
     if not a.no_autotune:
@@ -331,16 +370,7 @@ def main():
           file=sys.stderr, flush=True)
 
     # dominant kernel: the per-iteration phase with the most device time
-    sb = stream_bytes(X, R)
-    LDV = (R + 3) & ~3
-    v_bytes = X.J * LDV * 4
-    per_launch_bytes = {
-        # k_gamma: X once, F read + F write (next Procrustes step), W and M3 written, V_t, V_{t+1}
-        "gamma": sb["x"] + 2 * sb["f"] + 2 * sb["w"] + 2 * v_bytes,
-        # k_mode2: X once, F and W read, V_t, M2 written
-        "mode2": sb["x"] + sb["f"] + sb["w"] + 2 * v_bytes,
-        "alpha": sb["x"] + sb["f"] + sb["w"] + v_bytes,
-    }
+    per_launch_bytes = algorithmic_bytes(X, R)
     cand = {k: prof[k] for k in ("gamma", "mode2") if prof[k][1] > 0}
     dom = max(cand, key=lambda k: cand[k][0])
     avg_ms = cand[dom][0] / cand[dom][1]
@@ -352,10 +382,13 @@ def main():
             rec = json.load(f)
         if rec.get("source_sha256") == kernel_source_hash():
             traffic = rec.get("bytes_per_launch")
+    copy_gbps = copy_rate_gbps()
     roof = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
-            "algorithmic_bytes_per_launch": per_launch_bytes[dom]}
+            "algorithmic_bytes_per_launch": per_launch_bytes[dom],
+            "copy_GBps_measured": round(copy_gbps, 1),
+            "frac_of_measured_copy": round(achieved / copy_gbps, 4)}
 
     cpu = None
     if a.cpu_subjects and not a.profile_only:
@@ -381,6 +414,7 @@ def main():
                    "nnz": X.nnz, "fit_after": fit,
                    "phase_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
                    "schedule": chosen.as_dict() if chosen else None,
+                   "hbm_footprint": footprint,
                    "paper_context": "SPARTan: 7.4 min/iteration at 63M nnz, R=10 (4x Xeon E5-4620 v4, "
                                     "NNLS-constrained, uniform sparsity)"},
         "roofline": roof,
