@@ -677,7 +677,8 @@ __device__ __forceinline__ void polar_rxr(const double* Cs, const double* w, con
 
 // Eigen-decomposition of C (Cs, row-major, group LDS).  Writes row p of Ec =
 // eigenvector at position p, sv[p] = sqrt(lambda_p) and isv[p] = 1/sqrt(lambda_p)
-// (both 0 for lambda_p <= tau_c * lambda_max).
+// (all three 0 for lambda_p <= tau_c * lambda_max; such rows only ever enter
+// multiplied by sv or isv).
 template <int R>
 __device__ __forceinline__ void factor_c(const double* Cs, double* Ec, double* sv, double* isv,
                                          double* dl, int c, int gbase, uint64_t gmask,
@@ -685,24 +686,28 @@ __device__ __forceinline__ void factor_c(const double* Cs, double* Ec, double* s
   constexpr int NC = Geo<R>::NC;
   double g[R], v[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    g[i] = (c < R) ? Cs[i * R + c] : 0.0;
-    v[i] = (i == c) ? 1.0 : 0.0;
-  }
-  jacobi_onesided<R>(g, v, c, gbase, gmask, true, tol, stop2, max_sweeps);
+  for (int i = 0; i < R; ++i) g[i] = (c < R) ? Cs[i * R + c] : 0.0;
+  // Jacobi on the columns of C's pivoted Cholesky factor (Ec's first R
+  // doubles and dl[0] are scratch until the results are written below): the
+  // converged columns are sigma_p u_p, eigenvectors u_p of C with eigenvalues
+  // sigma_p^2, found without accumulating the rotations
+  pivoted_cholesky<R>(g, c, true, Ec, reinterpret_cast<unsigned long long*>(dl), 1e-2 * tau_c);
+  jacobi_onesided<R, R, false>(g, v, c, gbase, gmask, true, tol, stop2, max_sweeps);
   double lam = 0.0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) lam = fma(v[i], g[i], lam);
+  for (int i = 0; i < R; ++i) lam = fma(g[i], g[i], lam);
   dl[c] = lam;
   wave_sync();
   double lmax = 0.0;
   for (int p = 0; p < NC; ++p) lmax = fmax(lmax, dl[p]);
   wave_sync();
   const bool keep = lam > tau_c * lmax && lam > 0.0;
+  const double s = sqrt(lam);
+  const double inv_s = keep ? 1.0 / s : 0.0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) Ec[c * R + i] = v[i];
-  sv[c] = keep ? sqrt(lam) : 0.0;
-  isv[c] = keep ? 1.0 / sqrt(lam) : 0.0;
+  for (int i = 0; i < R; ++i) Ec[c * R + i] = g[i] * inv_s;
+  sv[c] = keep ? s : 0.0;
+  isv[c] = inv_s;
   wave_sync();
 }
 
