@@ -161,44 +161,72 @@ __device__ __forceinline__ void gather_rows(const XS& X, const Subj& s, int i0, 
   }
 }
 
-// Two gathers of the same rows against two factor matrices (V_t and V_{t+1}).
-template <int R, class XS>
+// Two gathers of the same rows against two factor matrices (V_t and V_{t+1}),
+// stored as FP32 (the gathered values are FP32 sums, so nothing is lost):
+// row ii of X_k V0 at A0 + ii * R, row ii of X_k V1 at A1 + ii * LDV (16-byte
+// rows for the Gram's vector reads; the padding columns are zero).
+template <int R, int T, class XS>
 __device__ __forceinline__ void gather_rows2(const XS& X, const Subj& s, int i0, int n,
                                              const float* __restrict__ V0,
-                                             const float* __restrict__ V1, double* A0, double* A1,
+                                             const float* __restrict__ V1, float* A0, float* A1,
                                              int j) {
   constexpr int NC = Geo<R>::NC;
   constexpr int LDV = Geo<R>::LDV;
 #pragma nounroll
-  for (int ii = j; ii < n; ii += NC) {
-    float a0[LDV], a1[LDV];
+  for (int ib = 0; ib < n; ib += T * NC) {
+    // T rows per lane, their nonzeros walked together so that the T load
+    // chains (row bounds, column, V rows) are in flight at once
+    int zs[T], len[T];
 #pragma unroll
-    for (int c = 0; c < LDV; ++c) a0[c] = a1[c] = 0.f;
-    int zs, ze;
-    X.row(s, i0 + ii, zs, ze);
-    for (int z = zs; z < ze; ++z) {
-      const int col = X.colat(s, z);
-      const float x = X.valat(s, z);
-      const float* v0 = V0 + (size_t)col * LDV;
-      const float* v1 = V1 + (size_t)col * LDV;
+    for (int t = 0; t < T; ++t) {
+      const int ii = ib + j + t * NC;
+      int a = 0, b = 0;
+      if (ii < n) X.row(s, i0 + ii, a, b);
+      zs[t] = a;
+      len[t] = b - a;
+    }
+    float a0[T][LDV], a1[T][LDV];
 #pragma unroll
-      for (int q = 0; q < LDV / 4; ++q) {
-        const p2_f4 t = ldg4(v0 + 4 * q);
-        const p2_f4 u = ldg4(v1 + 4 * q);
-        a0[4 * q + 0] = fmaf(x, t.x, a0[4 * q + 0]);
-        a0[4 * q + 1] = fmaf(x, t.y, a0[4 * q + 1]);
-        a0[4 * q + 2] = fmaf(x, t.z, a0[4 * q + 2]);
-        a0[4 * q + 3] = fmaf(x, t.w, a0[4 * q + 3]);
-        a1[4 * q + 0] = fmaf(x, u.x, a1[4 * q + 0]);
-        a1[4 * q + 1] = fmaf(x, u.y, a1[4 * q + 1]);
-        a1[4 * q + 2] = fmaf(x, u.z, a1[4 * q + 2]);
-        a1[4 * q + 3] = fmaf(x, u.w, a1[4 * q + 3]);
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+      for (int c = 0; c < LDV; ++c) a0[t][c] = a1[t][c] = 0.f;
+    }
+    int steps = len[0];
+#pragma unroll
+    for (int t = 1; t < T; ++t) steps = max(steps, len[t]);
+    for (int u = 0; u < steps; ++u) {
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        if (u < len[t]) {
+          const int col = X.colat(s, zs[t] + u);
+          const float x = X.valat(s, zs[t] + u);
+          const float* v0 = V0 + (size_t)col * LDV;
+          const float* v1 = V1 + (size_t)col * LDV;
+#pragma unroll
+          for (int q = 0; q < LDV / 4; ++q) {
+            const p2_f4 tv = ldg4(v0 + 4 * q);
+            const p2_f4 uv = ldg4(v1 + 4 * q);
+            a0[t][4 * q + 0] = fmaf(x, tv.x, a0[t][4 * q + 0]);
+            a0[t][4 * q + 1] = fmaf(x, tv.y, a0[t][4 * q + 1]);
+            a0[t][4 * q + 2] = fmaf(x, tv.z, a0[t][4 * q + 2]);
+            a0[t][4 * q + 3] = fmaf(x, tv.w, a0[t][4 * q + 3]);
+            a1[t][4 * q + 0] = fmaf(x, uv.x, a1[t][4 * q + 0]);
+            a1[t][4 * q + 1] = fmaf(x, uv.y, a1[t][4 * q + 1]);
+            a1[t][4 * q + 2] = fmaf(x, uv.z, a1[t][4 * q + 2]);
+            a1[t][4 * q + 3] = fmaf(x, uv.w, a1[t][4 * q + 3]);
+          }
+        }
       }
     }
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-      A0[ii * R + c] = (double)a0[c];
-      A1[ii * R + c] = (double)a1[c];
+    for (int t = 0; t < T; ++t) {
+      const int ii = ib + j + t * NC;
+      if (ii < n) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) A0[ii * R + c] = a0[t][c];
+#pragma unroll
+        for (int c = 0; c < LDV; ++c) A1[ii * LDV + c] = c < R ? a1[t][c] : 0.f;
+      }
     }
   }
 }
@@ -228,29 +256,38 @@ __device__ __forceinline__ void gram_accum(const double* A, const double* B, int
   }
 }
 
-// Rows c of A0^T A1 and A1^T A1 together (one read of each A1 row).
+// Rows c of A0^T A1 and A1^T A1 together (one read of each A1 row), from the
+// FP32 rows gather_rows2 leaves in LDS; products and sums in FP64 (products of
+// FP32 values are exact in FP64).  FP32 rows halve the LDS bytes each lane
+// reads, which bound this loop when the rows were held as FP64.
 template <int R>
-__device__ __forceinline__ void gram_accum2(const double* A0, const double* A1, int n, int c,
+__device__ __forceinline__ void gram_accum2(const float* A0, const float* A1, int n, int c,
                                             double (&prow)[R], double (&crow)[R]) {
+  constexpr int LDV = Geo<R>::LDV;
   const int cc = c < R ? c : 0;
 #pragma nounroll
   for (int ii = 0; ii < n; ++ii) {
-    const double a0 = A0[ii * R + cc];
-    const double a1 = A1[ii * R + cc];
+    const double a0 = (double)A0[ii * R + cc];
+    const double a1 = (double)A1[ii * LDV + cc];
     if constexpr (R % 2 == 0) {
-      const double2* b = reinterpret_cast<const double2*>(A1 + ii * R);
+      const float4* b = reinterpret_cast<const float4*>(A1 + ii * LDV);
 #pragma unroll
-      for (int l = 0; l < R / 2; ++l) {
-        const double2 bb = b[l];
-        prow[2 * l] = fma(a0, bb.x, prow[2 * l]);
-        prow[2 * l + 1] = fma(a0, bb.y, prow[2 * l + 1]);
-        crow[2 * l] = fma(a1, bb.x, crow[2 * l]);
-        crow[2 * l + 1] = fma(a1, bb.y, crow[2 * l + 1]);
+      for (int l = 0; l < LDV / 4; ++l) {
+        const float4 bb = b[l];
+        const float e[4] = {bb.x, bb.y, bb.z, bb.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (4 * l + u < R) {
+            const double be = (double)e[u];
+            prow[4 * l + u] = fma(a0, be, prow[4 * l + u]);
+            crow[4 * l + u] = fma(a1, be, crow[4 * l + u]);
+          }
+        }
       }
     } else {
 #pragma unroll
       for (int l = 0; l < R; ++l) {
-        const double b = A1[ii * R + l];
+        const double b = (double)A1[ii * LDV + l];
         prow[l] = fma(a0, b, prow[l]);
         crow[l] = fma(a1, b, crow[l]);
       }

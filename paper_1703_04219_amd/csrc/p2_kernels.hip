@@ -74,13 +74,24 @@ extern __shared__ __align__(16) unsigned char p2_smem[];
 template <int R>
 struct PolarLds {
   static constexpr int NC = Geo<R>::NC;
-  static constexpr int CH = NC;
-  static constexpr int kA = 2 * CH * R;
+  static constexpr int LDV = Geo<R>::LDV;
+  // rows per lane and gather chunk, and rows per chunk: at small ranks one
+  // (a second row's accumulators would cost occupancy), two above
+  static constexpr int kRowsPerLane = R <= 10 ? 1 : 2;
+  static constexpr int CH = kRowsPerLane * NC;
+  // the chunk's rows, in doubles: FP32 rows of A (stride R) and A' (stride
+  // LDV) in gamma; FP64 rows (stride R) in alpha and the projection
+  static constexpr int kAf = (CH * (R + LDV) + 1) / 2;
+  static constexpr int kA = kAf > CH * R ? kAf : CH * R;
   static constexpr int kB = R * R + NC * R;
   static constexpr int kRegion = kA > kB ? kA : kB;
+  // waves per SIMD the pass kernels are compiled for: at small ranks three,
+  // which the LDS plan also allows, so that the register budget does not cut
+  // occupancy below what the LDS gives
+  static constexpr int kMinWaves = 1;
   static constexpr int kPerGroup = kRegion + 2 * R + NC;
-  static_assert(R % 2 == 1 || (kPerGroup % 2 == 0 && (CH * R) % 2 == 0),
-                "even-R group regions must stay 16-byte aligned");
+  static_assert(R % 2 == 1 || (kPerGroup % 2 == 0 && (CH * R) % 4 == 0),
+                "even-R group regions and the FP32 A' rows must stay 16-byte aligned");
 };
 
 template <int R>
@@ -233,7 +244,7 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
 // C'_k = A'_k^T A'_k.
 // ---------------------------------------------------------------------------
 template <int R, bool WARM>
-__global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
+__global__ void __launch_bounds__(256, PolarLds<R>::kMinWaves) k_gamma(const ProbDesc* __restrict__ P,
                                                 const Tile* __restrict__ T, int ntiles,
                                                 int* tickets, int parity, int do_next,
                                                 PolarParams pp) {
@@ -253,8 +264,8 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
   double* shFit = shM1 + R * R;
   double* gbuf = shFit + 2 + gslot * PolarLds<R>::kPerGroup;
   double* region = gbuf;
-  double* A0 = region;
-  double* A1 = region + CH * R;
+  float* A0 = reinterpret_cast<float*>(region);
+  float* A1 = A0 + CH * R;
   double* SF = region;          // F column-major (SF[col * R + row]), later C'
   double* SP = region + R * R;  // P rows, later the Jacobi scratch
   double* wv = gbuf + PolarLds<R>::kRegion;
@@ -292,7 +303,7 @@ __global__ void __launch_bounds__(256) k_gamma(const ProbDesc* __restrict__ P,
           for (int l = 0; l < R; ++l) prow[l] = crow[l] = 0.0;
           for (int i0 = 0; i0 < s.nrows; i0 += CH) {
             const int n = min(CH, s.nrows - i0);
-            gather_rows2<R>(X, s, i0, n, V0, V1, A0, A1, c);
+            gather_rows2<R, PolarLds<R>::kRowsPerLane>(X, s, i0, n, V0, V1, A0, A1, c);
             wave_sync();
             gram_accum2<R>(A0, A1, n, c, prow, crow);  // rows c of P = A^T A', C' = A'^T A'
             wave_sync();
