@@ -625,7 +625,10 @@ int runner_autotune(Runner& r, int32_t iters, parafac2_sched* chosen, double* be
       best = normalized(&sc);
     }
   }
-  const int m2shapes[][2] = {{0, 1}, {512, 2}, {768, 2}, {512, 3}, {256, 4}};
+  // (threads per block, blocks per CU): fewer or smaller blocks leave more of
+  // the LDS for hot columns (fewer global atomics, each of which is a memory
+  // transaction) at the price of occupancy
+  const int m2shapes[][2] = {{0, 1}, {768, 1}, {512, 1}, {512, 2}, {768, 2}, {512, 3}, {256, 4}};
   for (const auto& sh : m2shapes) {
     if (rc != P2_OK) break;
     parafac2_sched sc = best;
