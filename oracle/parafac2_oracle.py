@@ -102,6 +102,11 @@ def procrustes_q(X, H, w, V):
     Q_k = Z P^T (I_k x R, orthonormal columns)."""
     HSVt = (H * w) @ V.T  # R x J
     M = np.asarray((X @ HSVt.T).T)  # H S_k V^T X_k^T, R x I_k
+    if not np.any(M):
+        # H S_k V^T X_k^T = 0 (e.g. w_k = 0): every Q_k attains the objective,
+        # and this reading takes Q_k = 0, so that the subject contributes
+        # nothing (Y_k = 0) rather than an arbitrary orthonormal completion
+        return np.zeros((X.shape[0], H.shape[0]))
     P, s, Zt = np.linalg.svd(M, full_matrices=False)
     return Zt.T @ P.T
 

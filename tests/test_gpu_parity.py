@@ -136,6 +136,28 @@ def test_edge_ragged_subject_counts(K):
     _compare_one_iteration(X, 6, H0, V0, W0)
 
 
+def test_edge_zero_weight_subjects():
+    # a zero row of W makes B_k = 0: the GPU's Cholesky finds no positive
+    # pivot, so F_k = 0, Q_k = 0 and Y_k = 0 (the oracle's reading of a zero
+    # B_k); such subjects contribute nothing and their W rows stay zero
+    X, R = gen_config(1)
+    H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, 1, 1])
+    W0 = W0.copy()
+    dead = [0, 17, 101, X.K - 1]
+    W0[dead] = 0.0
+    ctx, _ = _compare_one_iteration(X, R, H0, V0, W0)
+    assert not np.any(ctx.W.cpu().numpy()[dead])
+    Q = ctx.q(0, X.K).cpu().numpy()
+    for k in dead:
+        assert not np.any(Q[X.subj_ptr[k]:X.subj_ptr[k + 1]])
+    _, _, _, hist = O.run(_xs(X), H0, V0, W0, 5, dense_loss=True)
+    ofits = np.array([h["fit"] for h in hist])
+    ctx5, gfits = _gpu_run(X, R, H0, V0, W0, 5)
+    print("fit oracle", ofits, "gpu", gfits, flush=True)
+    assert np.max(np.abs(gfits - ofits)) <= 1e-5
+    assert not np.any(ctx5.W.cpu().numpy()[dead])
+
+
 def test_get_q_matches_oracle_and_is_orthonormal():
     X, R = gen_config(1)
     H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, 1, 1])

@@ -318,6 +318,33 @@ def test_subject_permutation_invariance():
     np.testing.assert_allclose(b[3]["M3"], a[3]["M3"][perm], rtol=1e-11, atol=1e-12)
 
 
+def test_zero_weight_subject_contributes_nothing():
+    # a subject with w_k = 0 has H S_k V^T X_k^T = 0; taking Q_k = 0 it must
+    # leave M1, M2, H, V and every other subject's W row exactly as if it were
+    # absent (W^T W, M1 and M2 weight it by w_k = 0), and its own M3 and W rows
+    # are then zero (Y_k = 0)
+    X, R = _small(K=12, J=9, R=3, seed=81)
+    Xs = _xs(X)
+    H, V, W = _state(X, R, 81)
+    dead = [2, 7]
+    W[dead] = 0.0
+    live = [k for k in range(X.K) if k not in dead]
+    a = O.iterate(Xs, H, V, W)
+    b = O.iterate([Xs[k] for k in live], H, V, W[live])
+    for k in dead:
+        assert not np.any(a[3]["Q"][k])
+        assert not np.any(a[3]["Y"][k][1])
+    np.testing.assert_allclose(a[3]["M1"], b[3]["M1"], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(a[3]["M2"], b[3]["M2"], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(a[0], b[0], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(a[2][live], b[2], rtol=1e-11, atol=1e-12)
+    assert not np.any(a[3]["M3"][dead]) and not np.any(a[2][dead])
+    # the loss counts the dead subjects' whole norm, in both loss formulas
+    nx_dead = sum(float(Xs[k].multiply(Xs[k]).sum()) for k in dead)
+    np.testing.assert_allclose(a[3]["loss"], b[3]["loss"] + nx_dead, rtol=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # P-12: projection of new subjects onto fixed (V, H)
 # ---------------------------------------------------------------------------
