@@ -366,7 +366,9 @@ __device__ __forceinline__ void jacobi_step(double (&g)[N], double (&v)[R], doub
                                             bool lane_odd, bool done, double tol2, double stop2,
                                             bool& rot, bool& big) {
   constexpr int NC = Geo<R>::NC;
-  constexpr bool kKeepPartner = N <= 20;
+  // a copy of the partner column saves its second DPP exchange in the
+  // rotation; it fits the register budget when no rotations are accumulated
+  constexpr bool kKeepPartner = ACCUM ? N <= 20 : N <= 40;
   const int partner = ODD ? (lane_odd ? j + 1 : j - 1) : (j ^ 1);
   const bool act = !done && (!ODD || (j != 0 && j != NC - 1));
   const bool lower = j < partner;
