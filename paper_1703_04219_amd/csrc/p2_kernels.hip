@@ -609,10 +609,17 @@ __global__ void __launch_bounds__(256) k_mode2_reduce(const ProbDesc* __restrict
   const float* __restrict__ src = D.part;
   float* __restrict__ M2 = D.M2;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-    float acc = 0.f;
-    for (int t = 0; t < D.nparts; ++t) acc += glob(src)[(int64_t)t * n + q];
+    // four independent partial sums (fixed order, so the result does not
+    // depend on the launch) keep several of the strided loads in flight
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    int t = 0;
+    for (; t + 4 <= D.nparts; t += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += glob(src)[(int64_t)(t + u) * n + q];
+    }
+    for (; t < D.nparts; ++t) acc[0] += glob(src)[(int64_t)t * n + q];
     const int j = q / R, r = q - j * R;
-    glob(M2)[(size_t)j * LDV + r] += acc;
+    glob(M2)[(size_t)j * LDV + r] += (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
 }
 
