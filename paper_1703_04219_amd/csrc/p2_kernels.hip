@@ -1537,7 +1537,9 @@ hipError_t mode2_t(const BatchView& b, int parity, hipStream_t s) {
 template <int R>
 hipError_t gram_t(const BatchView& b, int which, int parity, hipStream_t s) {
   const int gpb = (256 / kWave) * Geo<R>::GPW;
-  const int gx = grid_for(which == 0 ? b.maxK : b.maxJ, gpb * 16);
+  // about 64 rows per lane group: each block ends with R^2 FP64 global
+  // atomics, which are memory transactions, so fewer and longer blocks
+  const int gx = grid_for(which == 0 ? b.maxK : b.maxJ, gpb * 64);
   hipLaunchKernelGGL(k_gram<R>, dim3(gx, b.np), dim3(256), sizeof(double) * R * R, s, b.desc,
                      which, parity);
   return hipGetLastError();
