@@ -314,6 +314,42 @@ def gen_planted(K: int, J: int, R: int, ik_range, seed, col_blocks: bool = False
 # batched workload: 64 independent problems of different sizes
 # ---------------------------------------------------------------------------
 
+def gen_limits_case(big_nnz: int = 65535, J: int = 65536, K: int = 16, R: int = 4,
+                    seed=(ROOT_SEED, 9)) -> Slices:
+    """An input at the limits of the compact on-device encoding: J columns
+    (65536 by default, with the top column J - 1 used) and subject 0 holding
+    exactly big_nnz nonzeros in rows of about 50; subjects 1.. have I_k in
+    [R, R + 10] and 1-6 uniform distinct columns per row.  Values in (0, 1]."""
+    rng = np.random.default_rng(list(seed))
+    rows = []  # one (sorted distinct columns) array per row
+    subj_ptr = [0]
+    n0 = -(-big_nnz // 50)
+    base, extra = divmod(big_nnz, n0)
+    for i in range(n0):
+        m = base + (1 if i < extra else 0)
+        cols = np.sort(rng.choice(J, size=m, replace=False))
+        if i == 0 and cols[-1] != J - 1:
+            cols[-1] = J - 1
+            cols = np.unique(cols)
+            while cols.shape[0] < m:  # keep the row length after the swap
+                extra_col = int(rng.integers(0, J - 1))
+                if extra_col not in cols:
+                    cols = np.sort(np.append(cols, extra_col))
+        rows.append(cols)
+    subj_ptr.append(len(rows))
+    for _ in range(1, K):
+        ik = int(rng.integers(R, R + 11))
+        for _ in range(ik):
+            m = int(rng.integers(1, 7))
+            rows.append(np.sort(rng.choice(J, size=m, replace=False)))
+        subj_ptr.append(len(rows))
+    row_ptr = np.zeros(len(rows) + 1, np.int64)
+    row_ptr[1:] = np.cumsum([r.shape[0] for r in rows])
+    col = np.concatenate(rows).astype(np.int32)
+    val = (1.0 - rng.random(col.shape[0])).astype(np.float32)
+    return Slices(J, np.asarray(subj_ptr, np.int64), row_ptr, col, val)
+
+
 def gen_batched_specs(n_problems: int = 64, seed=(ROOT_SEED, 4), k_scale: float = 1.0):
     """Sizes of the batched workload: K log-uniform in [1000, 50000] (times
     k_scale), J in {500,1000,2000,5000}, R in {5,10,20}, I_k in [R,100],

@@ -60,6 +60,20 @@ def test_validate_host_rejects_bad_input(case, field, fn, code, text):
     assert text in msg
 
 
+def test_validate_host_encoding_limits():
+    # 16-bit column ids and in-subject nonzero offsets: J = 65536 and a subject
+    # with 65535 nonzeros are accepted, one more of either is ENOTSUP
+    from datagen.synth import gen_limits_case
+    X = gen_limits_case()
+    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 4)
+    assert rc == B.P2_OK, msg
+    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J + 1, 4)
+    assert rc == B.P2_ENOTSUP and "J" in msg
+    Y = gen_limits_case(big_nnz=65536)
+    rc, msg = B.parafac2_validate_host(Y.subj_ptr, Y.row_ptr, Y.col, Y.val, Y.J, 4)
+    assert rc == B.P2_ENOTSUP and "65535" in msg
+
+
 def test_validate_host_rank_rules():
     X, _ = gen_config(1)  # I_k in [5, 20]
     rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 6)

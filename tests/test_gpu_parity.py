@@ -158,6 +158,16 @@ def test_edge_zero_weight_subjects():
     assert not np.any(ctx5.W.cpu().numpy()[dead])
 
 
+def test_edge_encoding_limits():
+    # the largest input the compact encoding takes: J = 65536 (16-bit column
+    # ids, the top column used) and one subject with exactly 65535 nonzeros
+    # (16-bit in-subject offsets) in about 1300 rows
+    from datagen.synth import gen_limits_case
+    X = gen_limits_case()
+    H0, V0, W0 = gen_init(X.J, X.K, 4, [170304219, 9, 1])
+    _compare_one_iteration(X, 4, H0, V0, W0)
+
+
 def test_get_q_matches_oracle_and_is_orthonormal():
     X, R = gen_config(1)
     H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, 1, 1])
