@@ -1,6 +1,6 @@
-"""GPU parity at the full sizes of the two large workloads, in the launch
-configuration bench.py times (the schedule its autotuner settles on and the
-default one).
+"""GPU parity at the full sizes of the large workloads, in the launch
+configurations bench.py times (the schedule its autotuner settles on and the
+default one), and of the 64-problem batch against its problems run alone.
 
 The oracle cannot run a whole iteration over a million subjects, so it checks
 what it can compute subject by subject, plus relations that hold at any size:
@@ -93,3 +93,41 @@ def test_full_size_sampled_parity(cfg, sched):
           f"oracle Q orthonormality {worst_orth:.1e}", flush=True)
     assert eh <= 1e-5 and ev <= 1e-5
     assert e3 <= 1e-4 and ew <= 1e-4
+
+
+def test_full_size_batch_equals_problems_alone():
+    # the 64-problem workload at full size (K log-uniform in [1000, 50000],
+    # R in {5, 10, 20}, about 348M nonzeros), batched in the schedule the
+    # bench's autotuner settles on (graph replay, dynamic tiles, 768-thread
+    # mode-2 blocks), against each problem run on its own context: one
+    # iteration from the same state agrees to 1e-5 (only the order of float
+    # atomics differs)
+    from datagen.synth import gen_batched_problem, gen_batched_specs
+    specs = gen_batched_specs(64)
+    probs = []
+    for i, sp in enumerate(specs):
+        X = gen_batched_problem(sp)
+        H0, V0, W0 = gen_init(X.J, X.K, sp["R"], [170304219, 4, 7, i])
+        probs.append((X, sp["R"], H0, V0, W0))
+    nnz = sum(p[0].nnz for p in probs)
+    print(f"64 problems, {nnz} nnz", flush=True)
+    alone = []
+    for X, R, H0, V0, W0 in probs:
+        c = B.Context(B.DeviceSlices.from_slices(X), R, H0, V0, W0)
+        c.iterate(1)
+        alone.append((c.H.cpu().numpy().copy(), c.V.cpu().numpy().copy(),
+                      c.W.cpu().numpy().copy()))
+        del c
+    torch.cuda.synchronize()
+    ctxs = [B.Context(B.DeviceSlices.from_slices(X), R, H0, V0, W0)
+            for X, R, H0, V0, W0 in probs]
+    batch = B.Batch(ctxs, B.make_sched(tile_rounds=2, dynamic=1, graph=1, m2_threads=768,
+                                       m2_blocks=1))
+    batch.iterate(1)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for c, ref in zip(ctxs, alone):
+        got = (c.H.cpu().numpy(), c.V.cpu().numpy(), c.W.cpu().numpy())
+        worst = max(worst, max(rel(x, y) for x, y in zip(got, ref)))
+    print(f"batched vs alone, worst factor difference {worst:.2e}", flush=True)
+    assert worst <= 1e-5
