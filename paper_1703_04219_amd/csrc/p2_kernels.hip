@@ -402,6 +402,12 @@ __global__ void __launch_bounds__(256, PolarLds<R>::kMinWaves) k_gamma(const Pro
 // ---------------------------------------------------------------------------
 constexpr int kMode2Threads = 1024;
 
+#ifndef P2_M2_T10
+#define P2_M2_T10 2
+#endif
+#ifndef P2_M2_NT10
+#define P2_M2_NT10 3
+#endif
 template <int R>
 struct Mode2Lds {
   // E_k in FP64, rows of stride NC (R rounded up to even, so that rows are
@@ -413,7 +419,10 @@ struct Mode2Lds {
   // lane may hold 256 VGPRs (the FP64 D row alone takes 2R of them)
   static constexpr int kMaxThreads = R <= 16 ? kMode2Threads : kMode2Threads / 2;
   // rows a lane gathers per step (register budget: T x LDV floats)
-  static constexpr int kRowsPerStep = R <= 6 ? 4 : (R <= 10 ? 3 : (R <= 20 ? 2 : 1));
+  static constexpr int kRowsPerStep = R <= 6 ? 4 : (R <= 10 ? P2_M2_T10 : (R <= 20 ? 2 : 1));
+  // most frequent columns whose partial sums each lane keeps in registers
+  // (as many as the register budget of the rank's block size allows)
+  static constexpr int kTopReg = R <= 10 ? P2_M2_NT10 : (R == 20 ? 3 : (R == 32 ? 1 : 0));
   // floats before the group buffers: the hot partial sums, rounded up so
   // that E rows are 16-byte aligned
   static constexpr int hot_floats(int hot) { return (hot * R + 3) & ~3; }
@@ -454,6 +463,18 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
     __syncthreads();
     for (int q = threadIdx.x; q < hot * R; q += blockDim.x) shM2[q] = 0.f;
     __syncthreads();
+    // the kTopReg most frequent columns (ids 0.. after the relabelling) are
+    // summed in registers per lane and added to the LDS partial sums once per
+    // tile: under a skewed column distribution many lanes of one atomic
+    // instruction hit the same address, and LDS atomics to one address
+    // serialise
+    constexpr int NT = Mode2Lds<R>::kTopReg;
+    float top[NT > 0 ? NT : 1][R];
+#pragma unroll
+    for (int u = 0; u < (NT > 0 ? NT : 1); ++u) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) top[u][q] = 0.f;
+    }
     if (L.live) {
       // H'(:, c) held as FP32: with E = F^T H' diag(w') formed in FP64, a
       // rounding dH of H' moves D = A E by Q_k dH diag(w'), and Q_k = A F^T
@@ -576,7 +597,14 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
             for (int z = zs[t]; z < ze[t]; ++z) {
               const int j = (z == zs[t]) ? j0[t] : (int)cl[z];
               const float x = (z == zs[t]) ? x0[t] : vl[z];
-              if (j < hot) {
+#pragma unroll
+              for (int u = 0; u < NT; ++u) {
+                const float xt = (j == u) ? x : 0.f;
+#pragma unroll
+                for (int q = 0; q < R; ++q) top[u][q] = fmaf(xt, (float)d[q], top[u][q]);
+              }
+              if (j < NT) {
+              } else if (j < hot) {
                 float* dst = shM2 + j * R;
 #pragma unroll
                 for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * (float)d[q]);
@@ -589,6 +617,14 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
           }
         }
         wave_sync();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      if (u < hot) {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+          if (top[u][q] != 0.f) atomicAdd(shM2 + u * R + q, top[u][q]);
       }
     }
     __syncthreads();
