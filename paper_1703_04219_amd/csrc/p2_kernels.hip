@@ -85,9 +85,10 @@ struct PolarLds {
   static constexpr int kA = kAf > CH * R ? kAf : CH * R;
   static constexpr int kB = R * R + NC * R;
   static constexpr int kRegion = kA > kB ? kA : kB;
-  // waves per SIMD the pass kernels are compiled for: at small ranks three,
-  // which the LDS plan also allows, so that the register budget does not cut
-  // occupancy below what the LDS gives
+  // minimum waves per SIMD in k_gamma's launch bound: none asked for.  At
+  // R = 10 the kernel fits three waves by itself (163 VGPRs without warm
+  // starts; two waves cost about 0.6 ms per launch of the K = 1M pass), and a
+  // bound asking for three changed its schedule and cost about 0.2 ms
   static constexpr int kMinWaves = 1;
   static constexpr int kPerGroup = kRegion + 2 * R + NC;
   static_assert(R % 2 == 1 || (kPerGroup % 2 == 0 && (CH * R) % 4 == 0),
