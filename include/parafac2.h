@@ -45,7 +45,7 @@ enum {
   P2_ENOMEM = -2,  /* workspace smaller than parafac2_workspace_size() asked for */
   P2_EDEVICE = -3, /* a HIP call failed; the context is then unusable           */
   P2_ESTATE = -4,  /* context or model is in a failed state                    */
-  P2_ENOTSUP = -5, /* valid input outside what this build supports (e.g. R)    */
+  P2_ENOTSUP = -5, /* valid input outside what the library supports (e.g. R)  */
   P2_EBUSY = -6    /* a server's request queue is full; poll and submit again   */
 };
 
@@ -62,7 +62,7 @@ typedef struct parafac2_model parafac2_model;
  * owns nonzeros [row_ptr[i], row_ptr[i+1]).  Columns are in [0, J) and
  * strictly increasing within a row; values are finite.  Empty rows are
  * accepted (they contribute nothing; the paper filters them, Sec.
- * "Challenges of PARAFAC2 on sparse data").  Limits of this build:
+ * "Challenges of PARAFAC2 on sparse data").  Limits of the library:
  * I_k >= R (the rank-R Procrustes factor needs I_k >= R), I_k <= 65535,
  * nnz of one subject <= 65535, J <= 65536. */
 typedef struct {
@@ -158,7 +158,7 @@ int parafac2_workspace_size(const parafac2_csr* X, int32_t R, const parafac2_opt
  *              256-byte aligned, borrowed until parafac2_destroy.
  * Synchronises the stream once (validation result and column statistics).
  * Errors: P2_EINVAL (shapes, data, small workspace), P2_ENOTSUP (R or sizes
- * outside this build), P2_EDEVICE. */
+ * outside the library's limits), P2_EDEVICE. */
 int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* H, float* V,
                   float* W, void* workspace, size_t ws_bytes, void* stream,
                   const parafac2_opts* opts);
@@ -205,7 +205,7 @@ enum {
 int parafac2_set_profiling(parafac2_ctx* c, int32_t on);
 int parafac2_get_profile(parafac2_ctx* c, double* ms, int64_t* launches);
 
-/* Launch configuration of this build (diagnostics for tests and tuning;
+/* Launch configuration of the compiled kernels (diagnostics for tests and tuning;
  * touches no GPU).  kernel: 0 Procrustes step of the first iteration,
  * 1 mode-3 / W update / next Procrustes step, 2 mode-2 scatter,
  * 3 projection, 4 Q assembly.  threads receives the workgroup size,
