@@ -64,7 +64,7 @@ typedef struct parafac2_model parafac2_model;
  * accepted (they contribute nothing; the paper filters them, Sec.
  * "Challenges of PARAFAC2 on sparse data").  Limits of the library:
  * I_k >= R (the rank-R Procrustes factor needs I_k >= R), I_k <= 65535,
- * nnz of one subject <= 65535, J <= 65536. */
+ * nnz of one subject <= 65535, J <= 65536, K <= 2^31 - 1. */
 typedef struct {
   int64_t K, J, n_rows, nnz;
   const int64_t* subj_ptr; /* [K+1]      */

@@ -53,7 +53,15 @@ struct ProbDesc {
   float* part;      // mode-2 hot partial sums: nparts slots of hot * R floats
   int32_t nparts;   // mode-2 tiles of this problem
   int32_t hot;      // mode-2 hot columns of this problem
+  const int32_t* order;  // subject at each position of the per-subject passes, or
+                         // nullptr for the natural order
 };
+
+// Subject handled at position pos of a tile.  The order only changes which
+// subjects share a wave; every per-subject array stays indexed by subject.
+__device__ __forceinline__ int64_t subject_at(const ProbDesc& D, int64_t pos) {
+  return D.order != nullptr ? (int64_t)glob(D.order)[pos] : pos;
+}
 
 // A range of subjects of one problem.  Tile arrays are padded to a multiple
 // of kBins with empty tiles (k0 == k1) and stored bin-interleaved: position t

@@ -62,6 +62,8 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 inline int ldv_of(int R) { return (R + 3) & ~3; }
 
 constexpr int kDefaultRounds = 4;
+// subjects per window of the per-subject pass order (sorted by row count within)
+constexpr int64_t kOrderWindow = 64;
 constexpr int kDefaultM2Capacity = 512;
 constexpr int kMaxM2Capacity = 4096;
 
@@ -85,7 +87,7 @@ int64_t mode2_parts(int64_t K, int R, int cap) {
 
 // Offsets of every piece of the context workspace.
 struct Plan {
-  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, V[2], F, M2, M3, E, small, err,
+  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, order, V[2], F, M2, M3, E, small, err,
       part, desc, tiles, m2tiles, tickets, iter, total;
   bool warm = false;
   int64_t cap_tiles = 0, cap_m2 = 0;  // tile capacities of the context's own runner
@@ -115,6 +117,7 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const p
   p.rank = take(sizeof(int32_t) * J);
   p.perm = take(sizeof(int32_t) * J);
   p.hist = take(sizeof(uint32_t) * J);
+  p.order = take(sizeof(int32_t) * K);
   p.V[0] = take(sizeof(float) * J * LDV);
   p.V[1] = take(sizeof(float) * J * LDV);
   p.F = take(sizeof(double) * (size_t)K * R * R);
@@ -226,6 +229,7 @@ struct parafac2_ctx {
     d.part = at<float>(plan.part);
     d.nparts = 0;  // set by the runner from its schedule
     d.hot = hot;
+    d.order = at<int32_t>(plan.order);
     return d;
   }
 };
@@ -757,6 +761,7 @@ static int validate_host_impl(const parafac2_csr* X, int32_t R, std::string& msg
     return P2_ENOTSUP;
   }
   if (X->J > 65536) { msg = "J > 65536 is not supported"; return P2_ENOTSUP; }
+  if (X->K > INT32_MAX) { msg = "K > 2^31 - 1 is not supported"; return P2_ENOTSUP; }
   if (!X->subj_ptr || !X->row_ptr || (X->nnz > 0 && (!X->col || !X->val))) {
     msg = "NULL array";
     return P2_EINVAL;
@@ -847,6 +852,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
     return fail(P2_EINVAL, "K, J, R must be >= 1");
   if (!p2::rank_supported(R)) return fail(P2_ENOTSUP, "R=%d is not built", R);
   if (X->J > 65536) return fail(P2_ENOTSUP, "J > 65536 is not supported");
+  if (X->K > INT32_MAX) return fail(P2_ENOTSUP, "K > 2^31 - 1 is not supported");
   if (X->n_rows < X->K * (int64_t)R) return fail(P2_EINVAL, "n_rows < K*R: some I_k < R");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(P2_EINVAL, "workspace must be 256-byte aligned");
@@ -920,6 +926,21 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   INIT_TRY(hipMemcpyAsync(c->at<int32_t>(plan.perm), perm.data(), sizeof(int32_t) * X->J,
                           hipMemcpyHostToDevice, s));
   INIT_TRY(hipMemcpyAsync(c->at<int32_t>(plan.rank), rank.data(), sizeof(int32_t) * X->J,
+                          hipMemcpyHostToDevice, s));
+  // Subject order of the per-subject passes.  The groups of a wave take
+  // consecutive positions and the wave runs until its largest subject is
+  // done, so within each window of kOrderWindow subjects the subjects go by
+  // decreasing row count (stable).  Windows keep every tile's and every XCD
+  // bin's mix of sizes as it was.
+  std::vector<int32_t> order(X->K);
+  std::iota(order.begin(), order.end(), 0);
+  for (int64_t w0 = 0; w0 < X->K; w0 += kOrderWindow) {
+    const int64_t w1 = std::min<int64_t>(X->K, w0 + kOrderWindow);
+    std::stable_sort(order.begin() + w0, order.begin() + w1, [&](int32_t a, int32_t b) {
+      return c->subj_host[a + 1] - c->subj_host[a] > c->subj_host[b + 1] - c->subj_host[b];
+    });
+  }
+  INIT_TRY(hipMemcpyAsync(c->at<int32_t>(plan.order), order.data(), sizeof(int32_t) * X->K,
                           hipMemcpyHostToDevice, s));
   double* sm = c->small();
   const p2::SmallLayout SL = p2::small_layout(R);

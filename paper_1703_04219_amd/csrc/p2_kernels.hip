@@ -193,7 +193,8 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
     for (int q = threadIdx.x; q < R * R; q += blockDim.x) shM1[q] = 0.0;
     __syncthreads();
     if (L.live) {
-      for (int64_t k = tile.k0 + gslot; k < tile.k1; k += gpb) {
+      for (int64_t pos = tile.k0 + gslot; pos < tile.k1; pos += gpb) {
+        const int64_t k = subject_at(D, pos);
         const Subj s = X.subj(k);
         {
           double crow[R];
@@ -295,7 +296,8 @@ __global__ void __launch_bounds__(256, PolarLds<R>::kMinWaves) k_gamma(const Pro
     __syncthreads();
     double fa = 0.0, fb = 0.0;
     if (L.live) {
-      for (int64_t k = tile.k0 + gslot; k < tile.k1; k += gpb) {
+      for (int64_t pos = tile.k0 + gslot; pos < tile.k1; pos += gpb) {
+        const int64_t k = subject_at(D, pos);
         const Subj s = X.subj(k);
         double crow[R];
         {
@@ -484,7 +486,8 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
       float hc[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) hc[q] = (float)glob(D.H)[q * R + cc];
-      for (int64_t k = tile.k0 + gslot; k < tile.k1; k += gpb) {
+      for (int64_t pos = tile.k0 + gslot; pos < tile.k1; pos += gpb) {
+        const int64_t k = subject_at(D, pos);
         const Subj s = X.subj(k);
         {
           // F_k (R x R doubles, F(q, p) at p * R + q) staged in the group's E

@@ -74,6 +74,19 @@ def test_validate_host_encoding_limits():
     assert rc == B.P2_ENOTSUP and "65535" in msg
 
 
+def test_validate_host_subject_count_limit():
+    # the per-subject passes visit subjects through a 32-bit position table;
+    # the count is checked before any array is read
+    import ctypes
+    c = B.Csr(2**31, 10, 2**31 * 4, 0, 0, 0, 0, 0)
+    buf = ctypes.create_string_buffer(512)
+    rc = B.load().parafac2_validate_host(ctypes.byref(c), 4, buf, 512)
+    assert rc == B.P2_ENOTSUP and "2^31" in buf.value.decode()
+    c = B.Csr(2**31 - 1, 10, (2**31 - 1) * 4, 0, 0, 0, 0, 0)
+    rc = B.load().parafac2_validate_host(ctypes.byref(c), 4, buf, 512)
+    assert rc == B.P2_EINVAL and "NULL" in buf.value.decode()
+
+
 def test_validate_host_rank_rules():
     X, _ = gen_config(1)  # I_k in [5, 20]
     rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 6)
