@@ -63,7 +63,7 @@ inline int ldv_of(int R) { return (R + 3) & ~3; }
 
 constexpr int kDefaultRounds = 4;
 // subjects per window of the per-subject pass order (sorted by row count within)
-constexpr int64_t kOrderWindow = 64;
+constexpr int64_t kOrderWindow = 256;
 constexpr int kDefaultM2Capacity = 512;
 constexpr int kMaxM2Capacity = 4096;
 
