@@ -930,8 +930,10 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   // Subject order of the per-subject passes.  The groups of a wave take
   // consecutive positions and the wave runs until its largest subject is
   // done, so within each window of kOrderWindow subjects the subjects go by
-  // decreasing row count (stable).  Windows keep every tile's and every XCD
-  // bin's mix of sizes as it was.
+  // decreasing row count (stable).  Windows are short against an XCD bin and
+  // a mode-2 tile, which keep their mix of sizes; the Procrustes tiles (about
+  // a hundred subjects) get runs of similar sizes, which the ticket schedule
+  // balances.
   std::vector<int32_t> order(X->K);
   std::iota(order.begin(), order.end(), 0);
   for (int64_t w0 = 0; w0 < X->K; w0 += kOrderWindow) {
