@@ -36,14 +36,19 @@ def parse():
                    help="1-3 one decomposition; 4 the 64-problem batch; 5 the serving trace")
     p.add_argument("--k-limit", type=int, default=None, help="only the first K subjects")
     p.add_argument("--cpu-subjects", type=int, default=-1,
-                   help="subjects in the oracle's timed sample (0 = skip; default: about 12 s "
-                        "of oracle work, 60,000 subjects at R=10 and 6,000 at R=40)")
+                   help="subjects in the oracle's timed sample (0 = skip; default: 200,000 "
+                        "at R=10 and 20,000 at R=40, 10-20 s on 16 host cores)")
     p.add_argument("--profile-only", action="store_true",
                    help="skip the CPU baseline (for profiler runs)")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default launch schedule instead of autotuning it")
     p.add_argument("--serve-seconds", type=float, default=10.0,
                    help="measured seconds of the serving trace (after 1 s of warm-up)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="default workload only: skip the R=40 iteration, the 64-problem batch "
+                        "and the serving trace that the default run adds to its line")
+    p.add_argument("--steps3", type=int, default=3,
+                   help="timed R=40 iterations in the default run's extras")
     p.add_argument("--copy-bytes", type=int, default=0,
                    help="only run a plain device-to-device copy of this many bytes (calibrates "
                         "the profiler's FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -96,45 +101,65 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def stream_bytes(X, R: int) -> dict:
-    """Algorithmic HBM bytes of one pass over the re-encoded slices and the
-    per-subject state, as used by the per-iteration kernels."""
+def design_bytes(X, R: int) -> dict:
+    """HBM bytes one launch of each per-iteration kernel moves as built: the
+    compact encoding of the slices (uint16 column + float32 value per nonzero,
+    uint16 row start per row, two int64 offsets per subject), F_k as a float64
+    R x R matrix per subject, W rows and the two V copies."""
     K, n_rows, nnz = X.K, X.n_rows, X.nnz
-    x = nnz * (2 + 4) + n_rows * 2 + (K + 1) * 16  # col16 + val, row starts, offsets
-    f = K * R * R * 8                              # F_k (float64 R x R)
+    x = nnz * (2 + 4) + n_rows * 2 + (K + 1) * 16
+    f = K * R * R * 8
     w = K * R * 4
-    return {"x": x, "f": f, "w": w}
+    v = X.J * ((R + 3) & ~3) * 4
+    return {"gamma": x + 2 * f + 2 * w + 2 * v,  # F read + written, W and M3 written
+            "mode2": x + f + w + 2 * v,
+            "alpha": x + f + w + v}
 
 
-def algorithmic_bytes(X, R: int) -> dict:
-    """Algorithmic HBM bytes of one launch of each per-iteration kernel."""
-    sb = stream_bytes(X, R)
-    LDV = (R + 3) & ~3
-    v_bytes = X.J * LDV * 4
-    return {
-        # k_gamma: X once, F read + F write (next Procrustes step), W and M3 written, V_t, V_{t+1}
-        "gamma": sb["x"] + 2 * sb["f"] + 2 * sb["w"] + 2 * v_bytes,
-        # k_mode2: X once, F and W read, V_t, M2 written
-        "mode2": sb["x"] + sb["f"] + sb["w"] + 2 * v_bytes,
-        "alpha": sb["x"] + sb["f"] + sb["w"] + v_bytes,
-    }
+def method_bytes(X, R: int) -> dict:
+    """Algorithmic HBM bytes per launch that the method itself needs: the
+    slices once at the reference encoding (int32 column + float32 value per
+    nonzero, int32 row offset per row, int64 offset per subject), the W rows
+    read or written and, between the two passes, a packed float32 symmetric
+    R x R state per subject (written by one pass, read by the other)."""
+    K, n_rows, nnz = X.K, X.n_rows, X.nnz
+    x = nnz * 8 + n_rows * 4 + K * 8
+    w = K * R * 4
+    state = K * (R * (R + 1) // 2) * 4
+    return {"gamma": x + 2 * w + 2 * state,  # W and M3 rows written; state read and written
+            "mode2": x + w + state,           # W rows and the state read
+            "alpha": x + w + state}
 
 
-def cpu_baseline(cfg: int, n_subjects: int):
-    from threadpoolctl import threadpool_limits
+def fp64_flops(X, R: int) -> dict:
+    """Algorithmic float64 work per launch of the Procrustes kernels: the two
+    R x R Grams of the gathered rows (2 I_k R^2 multiply-adds each, k_gamma),
+    or one (k_alpha), plus about 20 R^3 flops per subject for G = M C M^T, its
+    factorisation and eigen-solve and F = G^{-1/2} M (the middle of the
+    15-30 R^3 per subject range of a Jacobi solve of 5-8 sweeps)."""
+    rows = X.n_rows
+    polar = 20.0 * X.K * R ** 3
+    return {"gamma": 2 * 2.0 * rows * R * R + polar, "alpha": 2.0 * rows * R * R + polar}
 
-    from datagen import gen_config, gen_init
-    from oracle import parafac2_oracle as O
-    X, R = gen_config(cfg, k_limit=n_subjects)
-    H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, cfg, 1])
-    Xs = O.slices_to_list(X.subj_ptr, X.row_ptr, X.col, X.val, X.J)
-    with threadpool_limits(1):
+
+def cpu_baseline(X, R: int, cfg: int, n_subjects: int):
+    """The FP64 oracle (process-pool driver, one BLAS thread per worker, all
+    host CPUs up to 16) on the first n_subjects subjects of the workload."""
+    from datagen import gen_init, take_subjects
+    from oracle.parallel import Pool
+    Xs = take_subjects(X, 0, min(n_subjects, X.K))
+    H0, V0, W0 = gen_init(Xs.J, Xs.K, R, [170304219, cfg, 1])
+    with Pool(Xs.subj_ptr, Xs.row_ptr, Xs.col, Xs.val, Xs.J) as pool:
+        nx2 = pool.norm_x_sq()
         t0 = time.perf_counter()
-        O.iterate(Xs, H0, V0, W0, dense_loss=False)
+        pool.iterate(H0, V0, W0, nx2)
         dt = time.perf_counter() - t0
-    return {"value": X.nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {X.K} subjects of the workload ({X.nnz} nnz), one ALS iteration, "
-                      f"FP64 NumPy/LAPACK, one thread, {dt:.1f} s"}
+        workers = pool.workers
+    return {"value": Xs.nnz / dt, "unit": "nnz/s", "cores": workers, "kind": "oracle",
+            "host_cpus": os.cpu_count(),
+            "sample": f"first {Xs.K} subjects of the workload ({Xs.nnz} nnz), one ALS iteration, "
+                      f"FP64 NumPy/LAPACK oracle on {workers} worker processes "
+                      f"(one BLAS thread each), {dt:.1f} s"}
 
 
 def _request(X, k):
@@ -167,17 +192,38 @@ def replay(server, t, reqs, stop_after: float):
     return done
 
 
-def serving(a) -> dict:
-    import torch
+def _trace(server, t, reqs, warm: float, span: float) -> dict:
+    """Replay arrivals t (seconds, from 0) for warm + span seconds; latency of
+    each request arriving after warm = completion time - scheduled arrival."""
+    m = int(np.searchsorted(t, warm + span))
+    done = replay(server, t[:m], reqs[:m], stop_after=warm + span + 5.0)
+    server.drain()
+    lat = done - t[:m]
+    sel = t[:m] >= warm
+    ok = np.isfinite(lat) & sel
+    lat_ms = lat[ok] * 1e3
+    span_s = float(np.nanmax(done[sel]) - warm) if ok.any() else float("nan")
+    return {"p50_ms": float(np.percentile(lat_ms, 50)) if ok.any() else None,
+            "p99_ms": float(np.percentile(lat_ms, 99)) if ok.any() else None,
+            "completed": int(ok.sum()), "offered": int(sel.sum()),
+            "throughput_req_s": float(ok.sum() / span_s) if ok.any() else 0.0,
+            "measured_s": span}
 
+
+def serving(a) -> dict:
+    """Projection requests (R = 40, V 5000 x 40) against the continuous-batching
+    server and against the plain path (one request per batch, one slot):
+    Poisson arrivals at 2000 req/s and at 200 req/s, idle latency and
+    saturation throughput."""
     from datagen.synth import gen_serving_model, gen_serving_requests
     from paper_1703_04219_amd import binding as B
-    warm, dur, rate = 1.0, a.serve_seconds, 2000.0
+    warm, dur = 1.0, a.serve_seconds
     V, H = gen_serving_model()
-    t, X = gen_serving_requests(int((warm + dur) * rate))
-    reqs = [_request(X, k) for k in range(X.K)]
-    nnz_req = X.nnz / X.K
-    torch.cuda.set_device(0)
+    traces = {}
+    for rate, span in ((2000.0, dur), (200.0, max(2.0, dur / 2))):
+        t, X = gen_serving_requests(int((warm + span) * rate) + 1, rate=rate)
+        traces[rate] = (t, [_request(X, k) for k in range(X.K)], span, X.nnz / X.K)
+    reqs = traces[2000.0][1]
     model = B.Model(V, H)
     out = {}
     for name, kw in (("continuous", dict(slots=4, max_requests=512)),
@@ -187,7 +233,6 @@ def serving(a) -> dict:
             server.submit(k, *reqs[k])
         server.drain()
         server.poll()
-        # idle latency: one request at a time on an empty server
         idle = []
         for k in range(20):
             t1 = time.perf_counter()
@@ -195,7 +240,6 @@ def serving(a) -> dict:
             server.drain()
             server.poll()
             idle.append((time.perf_counter() - t1) * 1e3)
-        # saturation: a backlog of 1000 requests (500 for the plain path) drained
         nb = 1000 if kw["max_requests"] > 1 else 200
         t1 = time.perf_counter()
         for k in range(nb):
@@ -203,97 +247,192 @@ def serving(a) -> dict:
         server.drain()
         server.poll()
         sat = nb / (time.perf_counter() - t1)
-        # the Poisson trace: 1 s of warm-up arrivals, then the measured window
-        span = dur if kw["max_requests"] > 1 else min(dur, 2.0)
-        m = int(np.searchsorted(t, warm + span))
-        done = replay(server, t[:m], reqs[:m], stop_after=warm + span + 5.0)
-        server.drain()
-        lat = done - t[:m]
-        sel = t[:m] >= warm
-        ok = np.isfinite(lat) & sel
-        lat_ms = lat[ok] * 1e3
-        span_s = float(np.nanmax(done[sel]) - warm) if ok.any() else float("nan")
-        out[name] = {"p50_ms": float(np.percentile(lat_ms, 50)) if ok.any() else None,
-                     "p99_ms": float(np.percentile(lat_ms, 99)) if ok.any() else None,
-                     "completed": int(ok.sum()), "offered": int(sel.sum()),
-                     "throughput_req_s": float(ok.sum() / span_s) if ok.any() else 0.0,
-                     "measured_s": span,
-                     "idle_latency_ms_p50": float(np.median(idle)),
-                     "saturation_req_s": float(sat), "server": kw}
-        print(f"[bench] serving {name}: {out[name]}", file=sys.stderr, flush=True)
+        res = {"idle_latency_ms_p50": float(np.median(idle)), "saturation_req_s": float(sat),
+               "server": kw}
+        for rate, (t, rq, span, _) in traces.items():
+            # the plain path cannot keep up with 2000 req/s: a short window shows it
+            sp = span if (kw["max_requests"] > 1 or rate < 1000) else min(span, 2.0)
+            res[f"at_{int(rate)}_req_s"] = _trace(server, t, rq, warm, sp)
+        out[name] = res
+        print(f"[bench] serving {name}: {res}", file=sys.stderr, flush=True)
         server.close()
-    out["rate_req_s"] = rate
-    out["nnz_per_request"] = round(nnz_req, 1)
+    c = out["continuous"]["at_2000_req_s"]
+    out["p50_ms"], out["p99_ms"] = c["p50_ms"], c["p99_ms"]
+    out["rate_req_s"] = 2000.0
+    out["nnz_per_request"] = round(traces[2000.0][3], 1)
     out["R"] = int(V.shape[1])
+    model.close()
     return out
 
 
-def batched(a):
+def gen_batch_inputs():
+    """The 64-problem workload, drawn by a process pool (before the GPU runtime
+    starts: the pool forks)."""
     import concurrent.futures as cf
     import multiprocessing as mp
 
     from datagen.synth import gen_batched_problem, gen_batched_specs
-    from datagen import gen_init
     specs = gen_batched_specs()
     t0 = time.perf_counter()
     with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
                                 mp_context=mp.get_context("fork")) as ex:
         Xs = list(ex.map(gen_batched_problem, specs))
-    nnz = sum(X.nnz for X in Xs)
-    print(f"[bench] generated 64 problems, {nnz} nnz, in {time.perf_counter() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    print(f"[bench] generated 64 problems, {sum(X.nnz for X in Xs)} nnz, in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    return specs, Xs
+
+
+def batched(specs, Xs, steps: int, warmup: int, autotune: bool) -> dict:
+    """64 problems: one problem at a time (each context's own launches)
+    against one batch (one launch per rank class and kernel)."""
     import torch
 
+    from datagen import gen_init
     from paper_1703_04219_amd import binding as B
-    torch.cuda.set_device(0)
+    nnz = sum(X.nnz for X in Xs)
     ctxs = []
     for i, (sp, X) in enumerate(zip(specs, Xs)):
         H0, V0, W0 = gen_init(X.J, X.K, sp["R"], [170304219, 4, 1, i])
         ctxs.append(B.Context(B.DeviceSlices.from_slices(X), sp["R"], H0, V0, W0))
-    del Xs
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # one problem at a time (each context runs its own launches)
     for c in ctxs:
-        c.iterate(a.warmup, with_fit=False)
+        c.iterate(warmup, with_fit=False)
     torch.cuda.synchronize()
     e0.record()
     for c in ctxs:
-        c.iterate(a.steps, with_fit=False)
+        c.iterate(steps, with_fit=False)
     e1.record()
     torch.cuda.synchronize()
-    ms_single = e0.elapsed_time(e1) / a.steps
-    # the batch: one launch per rank class and kernel, autotuned schedule
+    ms_single = e0.elapsed_time(e1) / steps
     batch = B.Batch(ctxs, B.make_sched(graph=1))
-    chosen, tuned_ms = (None, None) if a.no_autotune else batch.autotune(2)
-    batch.iterate(a.warmup, with_fit=False)
+    chosen, tuned_ms = batch.autotune(2) if autotune else (None, None)
+    batch.iterate(warmup, with_fit=False)
     torch.cuda.synchronize()
     e0.record()
-    batch.iterate(a.steps, with_fit=False)
+    batch.iterate(steps, with_fit=False)
     e1.record()
     torch.cuda.synchronize()
-    ms_batch = e0.elapsed_time(e1) / a.steps
+    ms_batch = e0.elapsed_time(e1) / steps
     fits = batch.iterate(1)[0]
     print(f"[bench] batched {ms_batch:.3f} ms/iteration vs one problem at a time "
           f"{ms_single:.3f} ms; schedule {chosen.as_dict() if chosen else 'default'}",
           file=sys.stderr, flush=True)
-    out = {
-        "metric": "ALS-iteration nnz/s & % HBM roofline at R=10/40; p50/p99 projection latency",
-        "value": nnz / (ms_batch * 1e-3), "unit": "nnz/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 sparse products, f64 RxR", "data": "synthetic",
-        "config": {"workload": "c4_batched_64_problems", "problems": len(ctxs), "nnz": nnz,
-                   "K_total": int(sum(c.X.K for c in ctxs)),
-                   "ranks": {str(r): sum(1 for sp in specs if sp["R"] == r) for r in (5, 10, 20)},
-                   "one_problem_at_a_time_ms": ms_single,
-                   "one_problem_at_a_time_nnz_s": nnz / (ms_single * 1e-3),
-                   "speedup_vs_one_at_a_time": ms_single / ms_batch,
-                   "schedule": chosen.as_dict() if chosen else None,
-                   "autotune_ms_per_iteration": tuned_ms,
-                   "min_fit_after": float(np.min(fits))},
-        "roofline": None, "cpu_baseline": None,
-    }
-    print(json.dumps(out), flush=True)
+    out = {"workload": "c4_batched_64_problems", "problems": len(ctxs), "nnz": nnz,
+           "K_total": int(sum(c.X.K for c in ctxs)),
+           "ranks": {str(r): sum(1 for sp in specs if sp["R"] == r) for r in (5, 10, 20)},
+           "batched_ms_per_iteration": ms_batch, "batched_nnz_s": nnz / (ms_batch * 1e-3),
+           "one_problem_at_a_time_ms": ms_single,
+           "one_problem_at_a_time_nnz_s": nnz / (ms_single * 1e-3),
+           "speedup_vs_one_at_a_time": ms_single / ms_batch,
+           "schedule": chosen.as_dict() if chosen else None,
+           "autotune_ms_per_iteration": tuned_ms, "min_fit_after": float(np.min(fits))}
+    batch.close()
+    for c in ctxs:
+        c.close()
+    del ctxs, batch
+    torch.cuda.empty_cache()
+    return out
+
+
+def decomposition(X, R: int, cfg: int, steps: int, warmup: int, autotune: bool,
+                  sched=None, traffic_file=None) -> dict:
+    """Time `steps` ALS iterations of one decomposition after `warmup`, with the
+    library's per-launch HIP events on the context's stream; returns the
+    iteration time, the phases and the roofline of the Procrustes/mode-3
+    kernel (k_gamma) and of the mode-2 kernel."""
+    import torch
+
+    from datagen import gen_init
+    from paper_1703_04219_amd import binding as B
+    H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, cfg, 1])
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
+    dX = B.DeviceSlices.from_slices(X)
+    opts = B.make_opts(sched=sched) if sched is not None else None
+    ctx = B.Context(dX, R, H0, V0, W0, opts)
+    del dX  # the context re-encoded the input into its workspace
+    torch.cuda.synchronize()
+    footprint = {"steady_bytes": int(torch.cuda.memory_allocated() - base),
+                 "peak_bytes": int(torch.cuda.max_memory_allocated() - base),
+                 "workspace_bytes": int(ctx.ws_bytes)}
+    print(f"[bench] R={R} init done, workspace {ctx.ws_bytes / 2**30:.2f} GiB", file=sys.stderr,
+          flush=True)
+    chosen, tuned_ms = None, None
+    if autotune:
+        chosen, tuned_ms = ctx.autotune(2)
+        print(f"[bench] autotuned schedule {chosen.as_dict()} ({tuned_ms:.3f} ms/iteration)",
+              file=sys.stderr, flush=True)
+    if warmup:
+        ctx.iterate(warmup, with_fit=False)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    ctx.iterate(steps, with_fit=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    fit = float(ctx.iterate(1)[0])
+    torch.cuda.synchronize()
+    print(f"[bench] R={R}: {ms_step:.3f} ms/iteration, fit {fit:.6f}, phases "
+          + ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}ms x{v[1]}" for k, v in prof.items()),
+          file=sys.stderr, flush=True)
+    mb, db, fl = method_bytes(X, R), design_bytes(X, R), fp64_flops(X, R)
+    kernels = {}
+    for k in ("gamma", "mode2", "alpha"):
+        if prof[k][1] == 0:
+            continue
+        avg = prof[k][0] / prof[k][1]
+        rec = {"avg_launch_ms": round(avg, 4), "launches": prof[k][1],
+               "method_bytes_per_launch": mb[k], "design_bytes_per_launch": db[k],
+               "hbm_GBps": round(mb[k] / (avg * 1e-3) / 1e9, 1),
+               "hbm_frac": round(mb[k] / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "design_GBps": round(db[k] / (avg * 1e-3) / 1e9, 1)}
+        if k in fl:
+            tf = fl[k] / (avg * 1e-3) / 1e12
+            rec["fp64_flops_per_launch"] = fl[k]
+            rec["fp64_TFLOPs"] = round(tf, 2)
+            rec["fp64_frac"] = round(tf / FP64_PEAK_TFLOPS, 4)
+        kernels["k_" + k] = rec
+    traffic = None
+    if traffic_file and os.path.exists(traffic_file):
+        with open(traffic_file) as f:
+            rec = json.load(f)
+        if rec.get("source_sha256") == kernel_source_hash():
+            traffic = rec.get("bytes_per_launch")
+    out = {"K": X.K, "J": X.J, "R": R, "n_rows": X.n_rows, "nnz": X.nnz,
+           "ms_per_step": ms_step, "nnz_per_s": X.nnz / (ms_step * 1e-3), "fit_after": fit,
+           "phase_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
+           "kernels": kernels, "traffic_k_gamma": traffic,
+           "schedule": chosen.as_dict() if chosen else (sched.as_dict() if sched else None),
+           "autotune_ms_per_iteration": tuned_ms, "hbm_footprint": footprint}
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline_of(dec: dict, copy_gbps: float) -> dict:
+    """The roofline object of the dominant kernel (k_gamma, the Procrustes
+    step fused with mode 3): achieved = the method's bytes per launch over
+    the launch's average duration (HIP events on the context's stream)."""
+    g = dec["kernels"]["k_gamma"]
+    ach = g["hbm_GBps"]
+    return {"bound": "hbm", "kernel": "k_gamma", "achieved": ach, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": dec["traffic_k_gamma"],
+            "avg_launch_ms": g["avg_launch_ms"],
+            "algorithmic_bytes_per_launch": g["method_bytes_per_launch"],
+            "design_bytes_per_launch": g["design_bytes_per_launch"],
+            "design_GBps": g["design_GBps"],
+            "copy_GBps_measured": round(copy_gbps, 1),
+            "frac_of_measured_copy": round(ach / copy_gbps, 4)}
+
+
+METRIC = "ALS-iteration nnz/s & % HBM roofline at R=10/40; p50/p99 projection latency"
 
 
 def main():
@@ -305,118 +444,100 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
               "subject-sharded design is described but not built.", file=sys.stderr)
         sys.exit(2)
+    from datagen import CONFIGS, gen_config
     if a.config == 4:
-        batched(a)
+        specs, Xs = gen_batch_inputs()
+        import torch
+        torch.cuda.set_device(0)
+        res = batched(specs, Xs, a.steps, a.warmup, not a.no_autotune)
+        print(json.dumps({"metric": METRIC, "value": res["batched_nnz_s"], "unit": "nnz/s",
+                          "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+                          "ms_per_step": res["batched_ms_per_iteration"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f32 sparse products, f64 RxR", "data": "synthetic",
+                          "config": res, "roofline": None, "cpu_baseline": None}), flush=True)
         return
     if a.config == 5:
+        import torch
+        torch.cuda.set_device(0)
         res = serving(a)
-        c = res["continuous"]
+        c = res["continuous"]["at_2000_req_s"]
         print(json.dumps({
-            "metric": "ALS-iteration nnz/s & % HBM roofline at R=10/40; p50/p99 projection latency",
-            "value": c["p99_ms"], "unit": "ms (p99 latency)", "n_gpus": 1, "steps": c["completed"],
-            "warmup": 1, "ms_per_step": c["p50_ms"], "higher_is_better": False,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32 gather, f64 RxR",
-            "data": "synthetic", "config": {"workload": "c5_serving_2000req_s", **res},
+            "metric": METRIC, "value": c["p99_ms"], "unit": "ms (p99 latency)", "n_gpus": 1,
+            "steps": c["completed"], "warmup": 1, "ms_per_step": c["p50_ms"],
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 gather, f64 RxR", "data": "synthetic",
+            "config": {"workload": "c5_serving_2000req_s", **res},
             "roofline": None, "cpu_baseline": None}), flush=True)
         return
-    import torch
 
-    from datagen import CONFIGS, gen_config, gen_init
-    from paper_1703_04219_amd import binding as B
-
-    # draw the input before the GPU runtime starts (the generator forks workers)
+    # draw every input before the GPU runtime starts (the generators fork workers)
+    extras = a.config == 2 and a.k_limit is None and not a.no_extras
     t0 = time.perf_counter()
     X, R = gen_config(a.config, k_limit=a.k_limit)
-    H0, V0, W0 = gen_init(X.J, X.K, R, [170304219, a.config, 1])
     print(f"[bench] generated K={X.K} J={X.J} R={R} rows={X.n_rows} nnz={X.nnz} "
           f"in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    X3 = specs = Xb = None
+    if extras:
+        t0 = time.perf_counter()
+        X3, _ = gen_config(3)
+        print(f"[bench] generated the R=40 workload, nnz={X3.nnz}, in "
+              f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+        specs, Xb = gen_batch_inputs()
+    import torch
+
+    from paper_1703_04219_amd import binding as B
     torch.cuda.set_device(0)
-    dX = B.DeviceSlices.from_slices(X)
-    ctx = B.Context(dX, R, H0, V0, W0)
-    del dX  # the context re-encoded the input into its workspace
-    torch.cuda.synchronize()
-    # device memory held from here on: the workspace (re-encoded X, per-subject
-    # state, partial sums) and the factors; the peak includes the input copy
-    # that init reads
-    footprint = {"steady_bytes": int(torch.cuda.memory_allocated()),
-                 "peak_bytes": int(torch.cuda.max_memory_allocated()),
-                 "workspace_bytes": int(ctx.ws_bytes)}
-    print(f"[bench] init done, workspace {ctx.ws_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
-    chosen, tuned_ms = None, None
-    if not a.no_autotune:
-        chosen, tuned_ms = ctx.autotune(2)
-        print(f"[bench] autotuned schedule {chosen.as_dict()} ({tuned_ms:.3f} ms/iteration)",
-              file=sys.stderr, flush=True)
-    if a.warmup:
-        ctx.iterate(a.warmup, with_fit=False)
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-
-    ctx.set_profiling(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    ctx.iterate(a.steps, with_fit=False)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_total = e0.elapsed_time(e1)
-    prof = ctx.profile()
-    ctx.set_profiling(False)
-    ms_step = ms_total / a.steps
-    fit = float(ctx.iterate(1)[0])
-    torch.cuda.synchronize()
-    print(f"[bench] {ms_step:.3f} ms/iteration, fit {fit:.6f}, phases "
-          + ", ".join(f"{k}={v[0] / max(v[1], 1):.3f}ms x{v[1]}" for k, v in prof.items()),
-          file=sys.stderr, flush=True)
-
-    # dominant kernel: the per-iteration phase with the most device time
-    per_launch_bytes = algorithmic_bytes(X, R)
-    cand = {k: prof[k] for k in ("gamma", "mode2") if prof[k][1] > 0}
-    dom = max(cand, key=lambda k: cand[k][0])
-    avg_ms = cand[dom][0] / cand[dom][1]
-    achieved = per_launch_bytes[dom] / (avg_ms * 1e-3) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_k_{dom}_c{a.config}.json")
-    if os.path.exists(tfile) and a.k_limit is None:
-        with open(tfile) as f:
-            rec = json.load(f)
-        if rec.get("source_sha256") == kernel_source_hash():
-            traffic = rec.get("bytes_per_launch")
+    tfile = os.path.join(ROOT, "profiles", f"traffic_k_gamma_c{a.config}.json")
+    dec = decomposition(X, R, a.config, a.steps, a.warmup, not a.no_autotune,
+                        traffic_file=tfile if a.k_limit is None else None)
     copy_gbps = copy_rate_gbps()
-    roof = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
-            "algorithmic_bytes_per_launch": per_launch_bytes[dom],
-            "copy_GBps_measured": round(copy_gbps, 1),
-            "frac_of_measured_copy": round(achieved / copy_gbps, 4)}
+    roof = roofline_of(dec, copy_gbps)
 
     cpu = None
     if a.cpu_subjects and not a.profile_only:
         print("[bench] timing the oracle on a sample ...", file=sys.stderr, flush=True)
-        n_cpu = a.cpu_subjects if a.cpu_subjects > 0 else {1: X.K, 2: 60000, 3: 6000}[a.config]
-        cpu = cpu_baseline(a.config, min(n_cpu, X.K))
+        n_cpu = a.cpu_subjects if a.cpu_subjects > 0 else {1: X.K, 2: 200000, 3: 20000}[a.config]
+        cpu = cpu_baseline(X, R, a.config, n_cpu)
+        print(f"[bench] oracle: {cpu['value']:.3e} nnz/s on {cpu['cores']} workers",
+              file=sys.stderr, flush=True)
+
+    more = {}
+    if extras:
+        # R = 40 at full size, in the schedule the autotuner settles on there
+        # (tile_rounds 16, dynamic); R = 40 iterations take about 0.6 s each
+        dec3 = decomposition(X3, 40, 3, a.steps3, 1, False,
+                             sched=B.make_sched(tile_rounds=16, dynamic=1),
+                             traffic_file=os.path.join(ROOT, "profiles", "traffic_k_gamma_c3.json"))
+        dec3["workload"] = CONFIGS[3]["name"]
+        dec3["roofline"] = roofline_of(dec3, copy_gbps)
+        more["r40"] = dec3
+        del X3
+        more["batched"] = batched(specs, Xb, a.steps, a.warmup, not a.no_autotune)
+        del Xb
+        more["serving"] = serving(a)
 
     name = CONFIGS[a.config]["name"] + ("" if a.k_limit is None else f"_first{X.K}")
+    cfg = {"workload": name, **{k: dec[k] for k in ("K", "J", "R", "n_rows", "nnz", "fit_after",
+                                                     "phase_ms_per_launch", "kernels", "schedule",
+                                                     "hbm_footprint")},
+           "paper_context": "SPARTan: 7.4 min/iteration at 63M nnz, R=10 and 14 min at R=40 "
+                            "(4x Xeon E5-4620 v4, NNLS-constrained, uniform sparsity)",
+           **more}
     out = {
-        "metric": "ALS-iteration nnz/s & % HBM roofline at R=10/40; p50/p99 projection latency",
-        "value": X.nnz / (ms_step * 1e-3),
+        "metric": METRIC,
+        "value": X.nnz / (dec["ms_per_step"] * 1e-3),
         "unit": "nnz/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": dec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 sparse products, f64 RxR",
         "data": "synthetic",
-        "config": {"workload": name, "K": X.K, "J": X.J, "R": R, "n_rows": X.n_rows,
-                   "nnz": X.nnz, "fit_after": fit,
-                   "phase_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
-                   "schedule": chosen.as_dict() if chosen else None,
-                   "hbm_footprint": footprint,
-                   "paper_context": "SPARTan: 7.4 min/iteration at 63M nnz, R=10 (4x Xeon E5-4620 v4, "
-                                    "NNLS-constrained, uniform sparsity)"},
+        "config": cfg,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -42,7 +42,8 @@ extern "C" {
 enum {
   P2_OK = 0,
   P2_EINVAL = -1,  /* bad argument or input data (message says which)          */
-  P2_ENOMEM = -2,  /* workspace smaller than parafac2_workspace_size() asked for */
+  P2_ENOMEM = -2,  /* reserved: no call returns it (a workspace smaller than
+                      parafac2_workspace_size() asked for is P2_EINVAL)      */
   P2_EDEVICE = -3, /* a HIP call failed; the context is then unusable           */
   P2_ESTATE = -4,  /* context or model is in a failed state                    */
   P2_ENOTSUP = -5, /* valid input outside what the library supports (e.g. R)  */
@@ -63,8 +64,9 @@ typedef struct parafac2_model parafac2_model;
  * strictly increasing within a row; values are finite.  Empty rows are
  * accepted (they contribute nothing; the paper filters them, Sec.
  * "Challenges of PARAFAC2 on sparse data").  Limits of the library:
- * I_k >= R (the rank-R Procrustes factor needs I_k >= R), I_k <= 65535,
- * nnz of one subject <= 65535, J <= 65536, K <= 2^31 - 1. */
+ * I_k >= R (the rank-R Procrustes factor with orthonormal columns needs
+ * I_k >= R), I_k <= 65535, nnz of one subject <= 65535, J <= 65536,
+ * K <= 2^31 - 1. */
 typedef struct {
   int64_t K, J, n_rows, nnz;
   const int64_t* subj_ptr; /* [K+1]      */
@@ -167,11 +169,24 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
  * step, the mode-1 MTTKRP and H update, the mode-2 MTTKRP and V update, the
  * mode-3 MTTKRP and W update (Algorithm "CP-ALS" order; H and V columns
  * normalised, W keeps the scale).  On return H, V and W hold the new state.
- * fit_host (host, n_iters entries, or NULL) receives per iteration
- * fit = 1 - loss / sum_k ||X_k||_F^2 with
- * loss = sum_k ||X_k - Q_k H S_k V^T||_F^2 evaluated after the W update.
- * Enqueues on the context's stream; synchronises only if fit_host != NULL. */
-int parafac2_iterate(parafac2_ctx* c, int32_t n_iters, double* fit_host);
+ * loss_host (host, n_iters entries, or NULL) receives per iteration
+ * loss = sum_k ||X_k - Q_k H S_k V^T||_F^2 (the objective of Sec. "Classical
+ * Algorithm for PARAFAC2") evaluated after the W update, and fit_host (host,
+ * n_iters entries, or NULL) fit = 1 - loss / sum_k ||X_k||_F^2.
+ * Enqueues on the context's stream; synchronises only if fit_host or
+ * loss_host is non-NULL (one device-to-host copy each). */
+int parafac2_iterate(parafac2_ctx* c, int32_t n_iters, double* fit_host, double* loss_host);
+
+/* Iterate until convergence (Algorithm "PARAFAC2-ALS", "while convergence
+ * criterion is not met"; the paper leaves the criterion open): stop after
+ * iteration t >= 2 when |loss_{t-1} - loss_t| <= tol * loss_{t-1} (or the
+ * loss is 0), or after max_iters iterations.  *n_done (host) receives the
+ * iterations run; fit_host and loss_host (host, max_iters entries, or NULL)
+ * receive the first *n_done values as for parafac2_iterate.  Synchronises the
+ * stream after every iteration to read its loss.  tol >= 0, max_iters >= 0,
+ * else P2_EINVAL. */
+int parafac2_iterate_until(parafac2_ctx* c, int32_t max_iters, double tol, int32_t* n_done,
+                           double* fit_host, double* loss_host);
 
 /* The three MTTKRPs of the last iteration (equations (mttkrp1), (mttkrp2),
  * (mttkrp3)), for parity checks.  Device pointers, any may be NULL:
@@ -184,6 +199,13 @@ int parafac2_get_mttkrp(parafac2_ctx* c, double* M1, float* M2, float* M3);
  * the rows of those subjects, (subj_ptr[k1] - subj_ptr[k0]) x R, row-major.
  * P2_ESTATE if no iteration has run since init. */
 int parafac2_get_q(parafac2_ctx* c, int64_t k0, int64_t k1, float* Q);
+
+/* U_k = Q_k H (Algorithm "PARAFAC2-ALS", ENSURE: the factors {U_k} after
+ * the loop; Sec. "Model": X_k ~ U_k S_k V^T) for subjects [k0, k1), with Q_k
+ * from the last Procrustes step and the context's current H.  U (device,
+ * float32) receives (subj_ptr[k1] - subj_ptr[k0]) x R rows, row-major.
+ * P2_ESTATE if no iteration has run since init. */
+int parafac2_get_u(parafac2_ctx* c, int64_t k0, int64_t k1, float* U);
 
 /* Per-phase device timing (for benchmarks).  While profiling is on, every
  * kernel launch of parafac2_iterate is bracketed by HIP events recorded on the
@@ -259,10 +281,12 @@ int parafac2_batch_create(parafac2_batch** out, parafac2_ctx* const* ctxs, int32
                           void* workspace, size_t ws_bytes, void* stream,
                           const parafac2_sched* sched);
 
-/* n_iters iterations of every context of the batch.  fit_host (host, or
- * NULL) receives n_iters x n fits, entry [i * n + b] for iteration i of
- * context b.  Each context's H, V, W are updated as by parafac2_iterate. */
-int parafac2_batch_iterate(parafac2_batch* b, int32_t n_iters, double* fit_host);
+/* n_iters iterations of every context of the batch.  fit_host and
+ * loss_host (host, or NULL) receive n_iters x n values, entry [i * n + b] for
+ * iteration i of context b.  Each context's H, V, W are updated as by
+ * parafac2_iterate. */
+int parafac2_batch_iterate(parafac2_batch* b, int32_t n_iters, double* fit_host,
+                           double* loss_host);
 
 int parafac2_batch_set_sched(parafac2_batch* b, const parafac2_sched* sched);
 

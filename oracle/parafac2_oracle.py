@@ -26,7 +26,8 @@ Readings of points the paper leaves open (each is listed in the design notes):
 
 * Q-step SVD (garbled in the text): the SVD of the R x I_k matrix
   H S_k V^T X_k^T is written P diag(sigma) Z^T, and Q_k = Z P^T; the rank-R
-  truncation is the thin SVD (I_k >= R is required).
+  truncation is the thin SVD.  For I_k < R the thin SVD has I_k singular
+  values and Q_k (I_k x R) has orthonormal rows instead of columns.
 * Normalisation (Algorithm "CP-ALS", "Normalize columns"): H and V get unit
   2-norm columns after their updates and the norms are dropped; W is not
   normalised (S_k = diag(W(k,:)) carries the scale, Sec. "CP Decomposition").
@@ -99,9 +100,11 @@ def pinv_sym(N):
 def procrustes_q(X, H, w, V):
     """Q-step for one subject (Sec. "Classical Algorithm for PARAFAC2",
     objective (procrustes_obj)): SVD of H S_k V^T X_k^T = P diag(s) Z^T,
-    Q_k = Z P^T (I_k x R, orthonormal columns)."""
-    HSVt = (H * w) @ V.T  # R x J
-    M = np.asarray((X @ HSVt.T).T)  # H S_k V^T X_k^T, R x I_k
+    Q_k = Z P^T (I_k x R; orthonormal columns, or orthonormal rows when
+    I_k < R)."""
+    # H S_k V^T X_k^T, R x I_k, associated as H S_k (X_k V)^T so that only the
+    # rows of V at X_k's nonzero columns enter
+    M = ((np.asarray(X @ V) * w) @ H.T).T
     if not np.any(M):
         # H S_k V^T X_k^T = 0 (e.g. w_k = 0): every Q_k attains the objective,
         # and this reading takes Q_k = 0, so that the subject contributes
@@ -123,43 +126,65 @@ def y_slice(Q, X):
 # matricizations of Y (R x J x K) and the plain MTTKRP definitions
 # ---------------------------------------------------------------------------
 
-def unfold_y(Ys, R, J, n):
-    """Mode-n matricization of the intermediate tensor Y (R x J x K) as a
-    sparse matrix, with Kolda's column ordering:
+def unfold_coo(Ys, R, J, n):
+    """The nonzeros of the mode-n matricization of the intermediate tensor Y
+    (R x J x K), with Kolda's column ordering (Sec. "Tensors and Tensor
+    Operations"):
       n=1: R x (J*K), column j + J*k;
       n=2: J x (R*K), column r + R*k;
-      n=3: K x (R*J), column r + R*j."""
+      n=3: K x (R*J), column r + R*j.
+    Returns (rows, cols, vals, shape); only the nonzero columns of each Y_k
+    are stored (all other entries of Y are zero)."""
     K = len(Ys)
-    rows, cols, vals = [], [], []
+    rows, cols, vals = [np.zeros(0, np.int64)], [np.zeros(0, np.int64)], [np.zeros(0)]
     for k, (cj, Yk) in enumerate(Ys):
         c = len(cj)
-        rr = np.repeat(np.arange(R), c)
-        jj = np.tile(cj, R)
+        rr = np.repeat(np.arange(R, dtype=np.int64), c)
+        jj = np.tile(np.asarray(cj, np.int64), R)
         v = Yk.reshape(-1)
         if n == 1:
             rows.append(rr); cols.append(jj + J * k)
         elif n == 2:
             rows.append(jj); cols.append(rr + R * k)
         else:
-            rows.append(np.full(R * c, k)); cols.append(rr + R * jj)
+            rows.append(np.full(R * c, k, dtype=np.int64)); cols.append(rr + R * jj)
         vals.append(v)
     shape = {1: (R, J * K), 2: (J, R * K), 3: (K, R * J)}[n]
-    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                         shape=shape)
+    return np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), shape
+
+
+def unfold_y(Ys, R, J, n):
+    """Mode-n matricization of Y as a sparse matrix (see unfold_coo)."""
+    rows, cols, vals, shape = unfold_coo(Ys, R, J, n)
+    return sp.csr_matrix((vals, (rows, cols)), shape=shape)
+
+
+def khatri_rao_rows(A, B, idx):
+    """Rows idx of the Khatri-Rao product A (.) B: row k*B.shape[0] + j is
+    A[k, :] * B[j, :]."""
+    nb = B.shape[0]
+    idx = np.asarray(idx, np.int64)
+    return A[idx // nb] * B[idx % nb]
 
 
 def mttkrp(Ys, H, V, W, n):
     """Plain definitions: M1 = Y_(1)(W (.) V) (mttkrp1), M2 = Y_(2)(W (.) H)
-    (mttkrp2), M3 = Y_(3)(V (.) H) (mttkrp3)."""
-    R, J, K = H.shape[0], V.shape[0], W.shape[0]
-    Yn = unfold_y(Ys, R, J, n)
+    (mttkrp2), M3 = Y_(3)(V (.) H) (mttkrp3).  The product is taken over the
+    columns of Y_(n) that hold a nonzero, with the matching rows of the
+    Khatri-Rao product; the other rows of that product multiply zero columns
+    of Y_(n) and are not formed (for a million subjects the full product has
+    K*J rows)."""
+    R, J = H.shape[0], V.shape[0]
+    rows, cols, vals, shape = unfold_coo(Ys, R, J, n)
+    used, inv = np.unique(cols, return_inverse=True)
+    Yu = sp.csr_matrix((vals, (rows, inv.reshape(-1))), shape=(shape[0], used.shape[0]))
     if n == 1:
-        kr = khatri_rao(W, V)
+        kr = khatri_rao_rows(W, V, used)
     elif n == 2:
-        kr = khatri_rao(W, H)
+        kr = khatri_rao_rows(W, H, used)
     else:
-        kr = khatri_rao(V, H)
-    return np.asarray(Yn @ kr)
+        kr = khatri_rao_rows(V, H, used)
+    return np.asarray(Yu @ kr)
 
 
 def mttkrp_per_slice(Ys, H, V, W, n):
@@ -248,6 +273,29 @@ def run(Xs, H, V, W, n_iter, dense_loss=True):
         H, V, W, info = iterate(Xs, H, V, W, nx2, dense_loss)
         hist.append(info)
     return H, V, W, hist
+
+
+def run_until(Xs, H, V, W, max_iter, tol, dense_loss=False):
+    """Iterate while the convergence criterion is not met (Algorithm
+    "PARAFAC2-ALS"; the paper leaves the criterion open).  The reading taken
+    here: stop after iteration t >= 2 once the loss decreased by at most
+    tol * loss_{t-1} (or reached 0), else after max_iter iterations."""
+    nx2 = norm_x_sq(Xs)
+    hist = []
+    for t in range(max_iter):
+        H, V, W, info = iterate(Xs, H, V, W, nx2, dense_loss)
+        hist.append(info)
+        if t > 0:
+            prev, cur = hist[-2]["loss"], info["loss"]
+            if cur <= 0.0 or abs(prev - cur) <= tol * abs(prev):
+                break
+    return H, V, W, hist
+
+
+def u_factors(Qs, H):
+    """U_k = Q_k H for every subject (Algorithm "PARAFAC2-ALS", after the
+    loop; Sec. "Model": X_k is approximated by U_k S_k V^T)."""
+    return [Q @ H for Q in Qs]
 
 
 # ---------------------------------------------------------------------------

@@ -80,9 +80,12 @@ def load(path: str = LIB_PATH):
         "parafac2_validate_host": (ctypes.c_int, [P(Csr), i32, ctypes.c_char_p, sz]),
         "parafac2_workspace_size": (ctypes.c_int, [P(Csr), i32, P(Opts), P(sz)]),
         "parafac2_init": (ctypes.c_int, [P(vp), P(Csr), i32, vp, vp, vp, vp, sz, vp, P(Opts)]),
-        "parafac2_iterate": (ctypes.c_int, [vp, i32, P(ctypes.c_double)]),
+        "parafac2_iterate": (ctypes.c_int, [vp, i32, P(ctypes.c_double), P(ctypes.c_double)]),
+        "parafac2_iterate_until": (ctypes.c_int, [vp, i32, ctypes.c_double, P(i32),
+                                                  P(ctypes.c_double), P(ctypes.c_double)]),
         "parafac2_get_mttkrp": (ctypes.c_int, [vp, vp, vp, vp]),
         "parafac2_get_q": (ctypes.c_int, [vp, i64, i64, vp]),
+        "parafac2_get_u": (ctypes.c_int, [vp, i64, i64, vp]),
         "parafac2_set_profiling": (ctypes.c_int, [vp, i32]),
         "parafac2_get_profile": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int64)]),
         "parafac2_launch_config": (ctypes.c_int, [i32, i32, P(i32), P(i64), P(i32)]),
@@ -95,7 +98,8 @@ def load(path: str = LIB_PATH):
         "parafac2_autotune": (ctypes.c_int, [vp, i32, P(Sched), P(ctypes.c_double)]),
         "parafac2_batch_workspace_size": (ctypes.c_int, [P(vp), i32, P(sz)]),
         "parafac2_batch_create": (ctypes.c_int, [P(vp), P(vp), i32, vp, sz, vp, P(Sched)]),
-        "parafac2_batch_iterate": (ctypes.c_int, [vp, i32, P(ctypes.c_double)]),
+        "parafac2_batch_iterate": (ctypes.c_int, [vp, i32, P(ctypes.c_double),
+                                                  P(ctypes.c_double)]),
         "parafac2_batch_set_sched": (ctypes.c_int, [vp, P(Sched)]),
         "parafac2_batch_autotune": (ctypes.c_int, [vp, i32, P(Sched), P(ctypes.c_double)]),
         "parafac2_batch_set_profiling": (ctypes.c_int, [vp, i32]),
@@ -120,7 +124,8 @@ def load(path: str = LIB_PATH):
 def exported_symbols() -> list:
     return ["parafac2_abi_version", "parafac2_last_error", "parafac2_validate_host",
             "parafac2_workspace_size", "parafac2_init", "parafac2_iterate",
-            "parafac2_get_mttkrp", "parafac2_get_q", "parafac2_set_profiling",
+            "parafac2_iterate_until", "parafac2_get_mttkrp", "parafac2_get_q",
+            "parafac2_get_u", "parafac2_set_profiling",
             "parafac2_get_profile", "parafac2_launch_config", "parafac2_destroy",
             "parafac2_model_workspace_size", "parafac2_model_create", "parafac2_project",
             "parafac2_model_destroy", "parafac2_set_sched", "parafac2_autotune",
@@ -273,10 +278,26 @@ class Context:
                                       _stream_handle(stream), ctypes.byref(self.opts)))
         self.handle = h
 
-    def iterate(self, n: int, with_fit: bool = True) -> Optional[np.ndarray]:
+    def iterate(self, n: int, with_fit: bool = True, with_loss: bool = False):
+        """Fits of the n iterations (or None); with_loss: (fits, losses)."""
         fit = (ctypes.c_double * n)() if with_fit else None
-        _check(self.lib.parafac2_iterate(self.handle, n, fit))
-        return np.array(fit[:], dtype=np.float64) if with_fit else None
+        loss = (ctypes.c_double * n)() if with_loss else None
+        _check(self.lib.parafac2_iterate(self.handle, n, fit, loss))
+        fits = np.array(fit[:], dtype=np.float64) if with_fit else None
+        if with_loss:
+            return fits, np.array(loss[:], dtype=np.float64)
+        return fits
+
+    def iterate_until(self, max_iters: int, tol: float):
+        """(fits, losses) of the iterations run until the relative loss change
+        is at most tol (parafac2_iterate_until)."""
+        fit = (ctypes.c_double * max(max_iters, 1))()
+        loss = (ctypes.c_double * max(max_iters, 1))()
+        nd = ctypes.c_int32(0)
+        _check(self.lib.parafac2_iterate_until(self.handle, max_iters, float(tol),
+                                               ctypes.byref(nd), fit, loss))
+        n = nd.value
+        return np.array(fit[:n], dtype=np.float64), np.array(loss[:n], dtype=np.float64)
 
     def mttkrp(self):
         import torch
@@ -294,6 +315,15 @@ class Context:
         Q = torch.empty((nrows, self.R), dtype=torch.float32, device=self.X.val.device)
         _check(self.lib.parafac2_get_q(self.handle, k0, k1, _ptr(Q)))
         return Q
+
+    def u(self, k0: int, k1: int):
+        """U_k = Q_k H of subjects [k0, k1) (parafac2_get_u)."""
+        import torch
+        sp = self.X.subj_ptr
+        nrows = int(sp[k1].item() - sp[k0].item())
+        U = torch.empty((nrows, self.R), dtype=torch.float32, device=self.X.val.device)
+        _check(self.lib.parafac2_get_u(self.handle, k0, k1, _ptr(U)))
+        return U
 
     PHASES = ("alpha", "solve_h", "mode2", "vupdate", "gamma", "fit")
 
@@ -352,7 +382,7 @@ class Batch:
         """Fits as an (n, len(ctxs)) array (or None)."""
         nc = len(self.ctxs)
         fit = (ctypes.c_double * (n * nc))() if with_fit else None
-        _check(self.lib.parafac2_batch_iterate(self.handle, n, fit))
+        _check(self.lib.parafac2_batch_iterate(self.handle, n, fit, None))
         return np.array(fit[:], dtype=np.float64).reshape(n, nc) if with_fit else None
 
     def set_sched(self, sched: Sched):
@@ -528,8 +558,16 @@ def parafac2_get_mttkrp(ctx: Context):
     return ctx.mttkrp()
 
 
+def parafac2_iterate_until(ctx: Context, max_iters: int, tol: float):
+    return ctx.iterate_until(max_iters, tol)
+
+
 def parafac2_get_q(ctx: Context, k0: int, k1: int):
     return ctx.q(k0, k1)
+
+
+def parafac2_get_u(ctx: Context, k0: int, k1: int):
+    return ctx.u(k0, k1)
 
 
 def parafac2_set_sched(ctx: Context, sched: Sched):

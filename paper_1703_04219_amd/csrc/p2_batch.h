@@ -15,7 +15,7 @@ constexpr int kFitRing = 1024;
 
 // Offsets (in doubles) of the per-problem small FP64 block.
 struct SmallLayout {
-  int M1, WtW, VtV, VtVraw, HtH, N2p, N3, N3p, inv, fitacc, nx2, fits, total;
+  int M1, WtW, VtV, VtVraw, HtH, N2p, N3, N3p, inv, fitacc, nx2, fits, losses, total;
 };
 
 __host__ __device__ constexpr SmallLayout small_layout(int R) {
@@ -33,7 +33,8 @@ __host__ __device__ constexpr SmallLayout small_layout(int R) {
   s.fitacc = s.inv + R;
   s.nx2 = s.fitacc + 2;
   s.fits = s.nx2 + 1;
-  s.total = s.fits + kFitRing;
+  s.losses = s.fits + kFitRing;
+  s.total = s.losses + kFitRing;
   return s;
 }
 

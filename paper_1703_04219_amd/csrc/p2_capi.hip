@@ -499,7 +499,7 @@ int runner_check(Runner& r) {
 }
 
 // n (<= kFitRing) iterations of every context of the runner.
-int runner_iterate_n(Runner& r, int32_t n, double* fit_host) {
+int runner_iterate_n(Runner& r, int32_t n, double* fit_host, double* loss_host) {
   if (!r.planned) P2_TRY(runner_prepare(r));
   hipStream_t s = r.stream;
   const bool prof = r.profiling;
@@ -529,28 +529,38 @@ int runner_iterate_n(Runner& r, int32_t n, double* fit_host) {
     HIP_TRY(p2::run_permute_rows(c->V(c->cur), c->Vuser, c->J, c->R, c->LDV, c->R,
                                  c->at<int32_t>(c->plan.perm), s));
   }
-  if (fit_host) {
-    const int nc = (int)r.ctxs.size();
-    std::vector<double> tmp((size_t)n * nc);
+  // the last n entries of the fit and loss rings, one copy each per context
+  const int nc = (int)r.ctxs.size();
+  double* outs[2] = {fit_host, loss_host};
+  std::vector<double> tmp[2];
+  for (int which = 0; which < 2; ++which) {
+    if (!outs[which]) continue;
+    tmp[which].resize((size_t)n * nc);
     for (int b = 0; b < nc; ++b) {
       parafac2_ctx* c = r.ctxs[b];
-      const double* fits = c->small() + p2::small_layout(c->R).fits;
+      const p2::SmallLayout SL = p2::small_layout(c->R);
+      const double* ring = c->small() + (which == 0 ? SL.fits : SL.losses);
       const int64_t first = (c->iters_done - n) % kFitRing;
       const int64_t n1 = std::min<int64_t>(n, kFitRing - first);
-      HIP_TRY(hipMemcpyAsync(tmp.data() + (size_t)b * n, fits + first, sizeof(double) * n1,
-                             hipMemcpyDeviceToHost, s));
+      double* dst = tmp[which].data() + (size_t)b * n;
+      HIP_TRY(hipMemcpyAsync(dst, ring + first, sizeof(double) * n1, hipMemcpyDeviceToHost, s));
       if (n1 < n)
-        HIP_TRY(hipMemcpyAsync(tmp.data() + (size_t)b * n + n1, fits, sizeof(double) * (n - n1),
-                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(dst + n1, ring, sizeof(double) * (n - n1), hipMemcpyDeviceToHost,
+                               s));
     }
+  }
+  if (fit_host || loss_host) {
     HIP_TRY(hipStreamSynchronize(s));
-    for (int b = 0; b < nc; ++b)
-      for (int32_t i = 0; i < n; ++i) fit_host[(size_t)i * nc + b] = tmp[(size_t)b * n + i];
+    for (int which = 0; which < 2; ++which)
+      if (outs[which])
+        for (int b = 0; b < nc; ++b)
+          for (int32_t i = 0; i < n; ++i)
+            outs[which][(size_t)i * nc + b] = tmp[which][(size_t)b * n + i];
   }
   return P2_OK;
 }
 
-int runner_iterate(Runner& r, int32_t n_iters, double* fit_host) {
+int runner_iterate(Runner& r, int32_t n_iters, double* fit_host, double* loss_host = nullptr) {
   if (n_iters < 0) return fail(P2_EINVAL, "n_iters < 0");
   if (n_iters == 0) return P2_OK;
   P2_TRY(runner_check(r));
@@ -558,7 +568,8 @@ int runner_iterate(Runner& r, int32_t n_iters, double* fit_host) {
   int32_t done = 0;
   while (done < n_iters) {
     const int32_t n = std::min<int32_t>(n_iters - done, kFitRing);
-    const int rc = runner_iterate_n(r, n, fit_host ? fit_host + (size_t)done * nc : nullptr);
+    const int rc = runner_iterate_n(r, n, fit_host ? fit_host + (size_t)done * nc : nullptr,
+                                    loss_host ? loss_host + (size_t)done * nc : nullptr);
     if (rc != P2_OK) {
       for (parafac2_ctx* c : r.ctxs) c->failed = true;
       return rc;
@@ -988,10 +999,31 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
 #undef INIT_TRY
 }
 
-int parafac2_iterate(parafac2_ctx* c, int32_t n_iters, double* fit_host) {
+int parafac2_iterate(parafac2_ctx* c, int32_t n_iters, double* fit_host, double* loss_host) {
   if (!c) return fail(P2_EINVAL, "ctx is NULL");
   if (c->failed) return fail(P2_ESTATE, "context is in a failed state");
-  return runner_iterate(*c->own, n_iters, fit_host);
+  return runner_iterate(*c->own, n_iters, fit_host, loss_host);
+}
+
+int parafac2_iterate_until(parafac2_ctx* c, int32_t max_iters, double tol, int32_t* n_done,
+                           double* fit_host, double* loss_host) {
+  if (!c || !n_done) return fail(P2_EINVAL, "NULL argument");
+  if (c->failed) return fail(P2_ESTATE, "context is in a failed state");
+  if (max_iters < 0 || !(tol >= 0.0)) return fail(P2_EINVAL, "max_iters < 0 or tol not >= 0");
+  *n_done = 0;
+  double prev = 0.0;
+  for (int32_t it = 0; it < max_iters; ++it) {
+    double fit = 0.0, loss = 0.0;
+    P2_TRY(runner_iterate(*c->own, 1, &fit, &loss));
+    if (fit_host) fit_host[it] = fit;
+    if (loss_host) loss_host[it] = loss;
+    *n_done = it + 1;
+    // relative decrease of the loss between consecutive iterations; a loss
+    // that reaches zero has converged as well
+    if (it > 0 && (loss <= 0.0 || std::fabs(prev - loss) <= tol * std::fabs(prev))) break;
+    prev = loss;
+  }
+  return P2_OK;
 }
 
 int parafac2_get_mttkrp(parafac2_ctx* c, double* M1, float* M2, float* M3) {
@@ -1012,7 +1044,7 @@ int parafac2_get_mttkrp(parafac2_ctx* c, double* M1, float* M2, float* M3) {
   return P2_OK;
 }
 
-int parafac2_get_q(parafac2_ctx* c, int64_t k0, int64_t k1, float* Q) {
+static int get_q_or_u(parafac2_ctx* c, int64_t k0, int64_t k1, float* Q, bool u) {
   if (!c || !Q) return fail(P2_EINVAL, "NULL argument");
   if (c->failed) return fail(P2_ESTATE, "context is in a failed state");
   if (k0 < 0 || k1 > c->K || k0 > k1) return fail(P2_EINVAL, "bad subject range");
@@ -1020,8 +1052,16 @@ int parafac2_get_q(parafac2_ctx* c, int64_t k0, int64_t k1, float* Q) {
     return fail(P2_ESTATE, "no completed Procrustes step to report");
   if (k0 == k1) return P2_OK;
   HIP_TRY(p2::run_getq(c->R, c->X, k0, k1, c->V(c->qv), c->at<double>(c->plan.F), Q,
-                       c->subj_host[k0], c->stream));
+                       c->subj_host[k0], u ? c->H : nullptr, c->stream));
   return P2_OK;
+}
+
+int parafac2_get_q(parafac2_ctx* c, int64_t k0, int64_t k1, float* Q) {
+  return get_q_or_u(c, k0, k1, Q, false);
+}
+
+int parafac2_get_u(parafac2_ctx* c, int64_t k0, int64_t k1, float* U) {
+  return get_q_or_u(c, k0, k1, U, true);
 }
 
 int parafac2_set_profiling(parafac2_ctx* c, int32_t on) {
@@ -1110,9 +1150,10 @@ int parafac2_batch_create(parafac2_batch** out, parafac2_ctx* const* ctxs, int32
   return P2_OK;
 }
 
-int parafac2_batch_iterate(parafac2_batch* b, int32_t n_iters, double* fit_host) {
+int parafac2_batch_iterate(parafac2_batch* b, int32_t n_iters, double* fit_host,
+                           double* loss_host) {
   if (!b) return fail(P2_EINVAL, "batch is NULL");
-  return runner_iterate(*b->r, n_iters, fit_host);
+  return runner_iterate(*b->r, n_iters, fit_host, loss_host);
 }
 
 int parafac2_batch_set_sched(parafac2_batch* b, const parafac2_sched* sched) {

@@ -76,8 +76,9 @@ hipError_t run_zero(const BatchView& b, int mask, hipStream_t s);
 hipError_t run_fit(const BatchView& b, hipStream_t s);
 hipError_t run_reset_tickets(const BatchView& b, hipStream_t s);
 hipError_t run_gram_rows(int R, const float* A, int64_t n, int lda, double* out, hipStream_t s);
+// Q_k (Hm == nullptr) or U_k = Q_k Hm of subjects [k0, k1)
 hipError_t run_getq(int R, const XEnc& X, int64_t k0, int64_t k1, const float* V, const double* F,
-                    float* Q, int64_t row0, hipStream_t s);
+                    float* Q, int64_t row0, const double* Hm, hipStream_t s);
 hipError_t run_project(int R, const XRaw& X, int64_t K, const float* V, const double* H,
                        const double* N3, const double* N3p, int n_steps, const float* w0,
                        float* Qout, float* wout, double* lossout, const PolarParams& pp,
@@ -86,7 +87,7 @@ hipError_t run_project(int R, const XRaw& X, int64_t K, const float* V, const do
 // init-time helpers (R-independent)
 hipError_t run_validate(const int64_t* subj_ptr, const int64_t* row_ptr, const int32_t* col,
                         const float* val, int64_t K, int64_t n_rows, int64_t nnz, int64_t J,
-                        int R, int* err, int64_t* zbase, int64_t* rbase, hipStream_t s);
+                        int min_rows, int* err, int64_t* zbase, int64_t* rbase, hipStream_t s);
 hipError_t run_encode(const int64_t* subj_ptr, const int64_t* row_ptr, const int32_t* col,
                       const float* val, int64_t K, int64_t nnz, const int32_t* rank,
                       uint16_t* rstart, uint16_t* col16, float* val_out, double* nx2,

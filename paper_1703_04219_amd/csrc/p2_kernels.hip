@@ -607,7 +607,8 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
 #pragma unroll
                 for (int q = 0; q < R; ++q) top[u][q] = fmaf(xt, (float)d[q], top[u][q]);
               }
-              if (j < NT) {
+              if (j < NT && j < hot) {
+                // summed in top[j] above, flushed once per tile below
               } else if (j < hot) {
                 float* dst = shM2 + j * R;
 #pragma unroll
@@ -929,8 +930,8 @@ __global__ void __launch_bounds__(256) k_zero(const ProbDesc* __restrict__ P, in
   }
 }
 
-// fit = 1 - loss / ||X||^2 into the ring slot of the iteration, which it
-// then counts as done; grid = problems
+// loss and fit = 1 - loss / ||X||^2 into the ring slots of the iteration,
+// which it then counts as done; grid = problems
 template <int R>
 __global__ void k_fit(const ProbDesc* __restrict__ P) {
   constexpr SmallLayout SL = small_layout(R);
@@ -941,6 +942,7 @@ __global__ void k_fit(const ProbDesc* __restrict__ P) {
     const double loss = nx2 - 2.0 * fa[0] + fa[1];
     const int64_t it = glob(D.iter)[0];
     glob(D.small)[SL.fits + (int)(it % kFitRing)] = 1.0 - loss / nx2;
+    glob(D.small)[SL.losses + (int)(it % kFitRing)] = loss;
     glob(D.iter)[0] = it + 1;
   }
 }
@@ -950,13 +952,14 @@ __global__ void k_fill_i32(int* __restrict__ p, int n, int v) {
 }
 
 // ---------------------------------------------------------------------------
-// Q_k = A_k F_k^T for subjects [k0, k1): rows written contiguously from Q.
+// Q_k = A_k F_k^T for subjects [k0, k1), or U_k = Q_k Hm = A_k (F_k^T Hm)
+// when Hm (R x R, row-major) is given: rows written contiguously from Q.
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ void __launch_bounds__(256) k_getq(XEnc X, int64_t k0, int64_t k1,
                                                const float* __restrict__ V,
                                                const double* __restrict__ F, float* __restrict__ Q,
-                                               int64_t row0) {
+                                               int64_t row0, const double* __restrict__ Hm) {
   constexpr int NC = Geo<R>::NC;
   constexpr int GPW = Geo<R>::GPW;
   constexpr int CH = NC;
@@ -973,8 +976,19 @@ __global__ void __launch_bounds__(256) k_getq(XEnc X, int64_t k0, int64_t k1,
     double fr[R];  // Q(i, c) = sum_p A(i, p) F(c, p), F(c, p) at p R + c
     const P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R;
     const int cc = c < R ? c : 0;
+    if (Hm) {
+      // U(i, c) = sum_q A(i, q) T(q, c), T = F^T Hm: T(q, c) = sum_p F(p, q) Hm(p, c)
 #pragma unroll
-    for (int p = 0; p < R; ++p) fr[p] = Fk[p * R + cc];
+      for (int q = 0; q < R; ++q) {
+        double t = 0.0;
+#pragma unroll
+        for (int p = 0; p < R; ++p) t = fma(Fk[q * R + p], glob(Hm)[p * R + cc], t);
+        fr[q] = t;
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < R; ++p) fr[p] = Fk[p * R + cc];
+    }
     for (int i0 = 0; i0 < s.nrows; i0 += CH) {
       const int n = min(CH, s.nrows - i0);
       gather_rows<R>(X, s, i0, n, V, gbuf, c);
@@ -1199,8 +1213,8 @@ __global__ void k_validate_rows(const int64_t* __restrict__ row_ptr, const int32
 
 __global__ void k_validate_subj(const int64_t* __restrict__ subj_ptr,
                                 const int64_t* __restrict__ row_ptr, int64_t K, int64_t n_rows,
-                                int R, int* __restrict__ err, int64_t* __restrict__ zbase,
-                                int64_t* __restrict__ rbase) {
+                                int min_rows, int* __restrict__ err,
+                                int64_t* __restrict__ zbase, int64_t* __restrict__ rbase) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= K;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = subj_ptr[k];
@@ -1217,7 +1231,7 @@ __global__ void k_validate_subj(const int64_t* __restrict__ subj_ptr,
         continue;
       }
       const int64_t I = r1 - r;
-      if (I < R) atomicOr(err, 32);
+      if (I < min_rows) atomicOr(err, 32);
       if (I > 65535) atomicOr(err, 64);
       if (r1 <= n_rows && row_ptr[r1] - row_ptr[r] > 65535) atomicOr(err, 128);
     }
@@ -1587,14 +1601,14 @@ hipError_t gram_t(const BatchView& b, int which, int parity, hipStream_t s) {
 
 template <int R>
 hipError_t getq_t(const XEnc& X, int64_t k0, int64_t k1, const float* V, const double* F, float* Q,
-                  int64_t row0, hipStream_t s) {
+                  int64_t row0, const double* Hm, hipStream_t s) {
   constexpr int T = getq_threads<R>();
   const int gpb = (T / kWave) * Geo<R>::GPW;
   const size_t lds = (size_t)gpb * getq_group<R>();
   hipError_t e = allow_lds(k_getq<R>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_getq<R>, dim3(grid_for(k1 - k0, gpb)), dim3(T), lds, s, X, k0, k1, V, F, Q,
-                     row0);
+                     row0, Hm);
   return hipGetLastError();
 }
 
@@ -1685,8 +1699,8 @@ int launch_threads(int R, int kernel) {
 }
 
 hipError_t run_getq(int R, const XEnc& X, int64_t k0, int64_t k1, const float* V, const double* F,
-                    float* Q, int64_t row0, hipStream_t s) {
-  P2_DISPATCH(R, return getq_t<RR>(X, k0, k1, V, F, Q, row0, s))
+                    float* Q, int64_t row0, const double* Hm, hipStream_t s) {
+  P2_DISPATCH(R, return getq_t<RR>(X, k0, k1, V, F, Q, row0, Hm, s))
 }
 
 hipError_t run_project(int R, const XRaw& X, int64_t K, const float* V, const double* H,
@@ -1699,9 +1713,9 @@ hipError_t run_project(int R, const XRaw& X, int64_t K, const float* V, const do
 
 hipError_t run_validate(const int64_t* subj_ptr, const int64_t* row_ptr, const int32_t* col,
                         const float* val, int64_t K, int64_t n_rows, int64_t nnz, int64_t J,
-                        int R, int* err, int64_t* zbase, int64_t* rbase, hipStream_t s) {
+                        int min_rows, int* err, int64_t* zbase, int64_t* rbase, hipStream_t s) {
   hipLaunchKernelGGL(k_validate_subj, dim3(grid1(K + 1)), dim3(256), 0, s, subj_ptr, row_ptr, K,
-                     n_rows, R, err, zbase, rbase);
+                     n_rows, min_rows, err, zbase, rbase);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_validate_rows, dim3(grid1(n_rows)), dim3(256), 0, s, row_ptr, col, val,

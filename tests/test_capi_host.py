@@ -141,3 +141,51 @@ def test_launch_config_rejects_unbuilt_rank():
     with pytest.raises(B.Parafac2Error) as e:
         B.parafac2_launch_config(7, 0)
     assert e.value.code == B.P2_ENOTSUP
+
+
+def test_init_rejects_a_short_workspace_before_touching_the_gpu():
+    # the workspace size is checked on the host, before any HIP call: a buffer
+    # one byte short of parafac2_workspace_size() is P2_EINVAL (the pointers
+    # are never dereferenced, so placeholders serve on a CPU-only host)
+    import ctypes
+    X, R = gen_config(1)
+    lib = B.load()
+    need = B.parafac2_workspace_size(X.K, X.J, X.n_rows, X.nnz, R)
+    fake = 1 << 20  # 256-byte aligned, never read
+    c = B.Csr(X.K, X.J, X.n_rows, X.nnz, fake, fake, fake, fake)
+    h = ctypes.c_void_p(0)
+    opts = B.make_opts()
+    rc = lib.parafac2_init(ctypes.byref(h), ctypes.byref(c), R, fake, fake, fake, fake, need - 1,
+                           None, ctypes.byref(opts))
+    assert rc == B.P2_EINVAL
+    assert "workspace too small" in lib.parafac2_last_error().decode()
+    assert not h.value
+    # a misaligned workspace is refused the same way
+    rc = lib.parafac2_init(ctypes.byref(h), ctypes.byref(c), R, fake, fake, fake, fake + 8, need,
+                           None, ctypes.byref(opts))
+    assert rc == B.P2_EINVAL and "aligned" in lib.parafac2_last_error().decode()
+
+
+@pytest.mark.parametrize("R", [10, 20, 40])
+def test_hot_column_requests_are_clamped_to_the_lds_plan(R):
+    # a hot-column count above what the mode-2 LDS plan holds is clamped on
+    # the host (the workspace of the partial sums is sized by the clamped
+    # count), so no launch can be planned over the LDS budget
+    _, _, max_hot = B.parafac2_launch_config(R, 2)
+    assert 0 < max_hot
+    sizes = dict(K=200_000, J=5000, n_rows=1_000_000, nnz=2_000_000, R=R)
+    dflt = B.parafac2_workspace_size(**sizes)
+    huge = B.parafac2_workspace_size(**sizes, opts=B.make_opts(hot_cols=10**6))
+    at_max = B.parafac2_workspace_size(**sizes, opts=B.make_opts(hot_cols=max_hot))
+    none = B.parafac2_workspace_size(**sizes, opts=B.make_opts(hot_cols=-1))
+    assert huge == at_max == dflt
+    assert none < dflt
+
+
+def test_iterate_rejects_null_handles():
+    lib = B.load()
+    import ctypes
+    nd = ctypes.c_int32(0)
+    assert lib.parafac2_iterate(None, 1, None, None) == B.P2_EINVAL
+    assert lib.parafac2_iterate_until(None, 5, 1e-3, ctypes.byref(nd), None, None) == B.P2_EINVAL
+    assert lib.parafac2_get_u(None, 0, 1, None) == B.P2_EINVAL

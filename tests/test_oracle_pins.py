@@ -368,3 +368,127 @@ def test_projection_loss_monotone_over_steps():
         losses = [O.project(Xs[k], V, H, n_steps=s)[2] for s in range(1, 8)]
         for a, b in zip(losses, losses[1:]):
             assert b <= a * (1 + 1e-12) + 1e-14
+
+
+# ---------------------------------------------------------------------------
+# input decoding, projection brute force, economy Procrustes, convergence, U_k
+# ---------------------------------------------------------------------------
+
+def test_slices_to_list_stacks_back_to_the_concatenated_csr():
+    # the per-subject slices, stacked in order, are the concatenated CSR itself
+    # (built here straight from the arrays, without the oracle's decoding)
+    X = gen_slices(37, 23, (1, 9), _poisson_plus_one(2.0), "zipf", [4711])
+    Xs = _xs(X)
+    assert len(Xs) == X.K
+    assert [x.shape for x in Xs] == [(int(i), X.J) for i in X.I()]
+    whole = sp.csr_matrix((X.val.astype(np.float64), X.col, X.row_ptr), shape=(X.n_rows, X.J))
+    stacked = sp.vstack(Xs).tocsr()
+    assert (stacked != whole).nnz == 0
+    # and each slice is the rows of its subject, densely
+    dense = whole.toarray()
+    for k in (0, 5, X.K - 1):
+        np.testing.assert_array_equal(Xs[k].toarray(), dense[X.subj_ptr[k]:X.subj_ptr[k + 1]])
+
+
+def _project_bruteforce(Xd, V, H, n_steps):
+    """n_steps alternations, each written out from scratch: the polar factor of
+    B = X V diag(w) H^T from a full SVD, then w from least squares of X on the
+    R rank-one terms (Q H(:, r)) V(:, r)^T."""
+    R = H.shape[0]
+    w = np.ones(R)
+    Q = None
+    for _ in range(n_steps):
+        B = Xd @ V @ np.diag(w) @ H.T
+        U, s, Vt = np.linalg.svd(B, full_matrices=False)
+        Q = U @ Vt
+        terms = np.stack([np.outer(Q @ H[:, r], V[:, r]).ravel() for r in range(R)], axis=1)
+        w = np.linalg.lstsq(terms, Xd.ravel(), rcond=None)[0]
+    return Q, w, float(np.sum((Xd - Q @ H @ np.diag(w) @ V.T) ** 2))
+
+
+def test_projection_matches_svd_lstsq_bruteforce():
+    X, R = _small(K=5, J=14, R=3, ik=(5, 9), seed=93)
+    Xs = _xs(X)
+    rng = np.random.default_rng(93)
+    V, H = rng.random((X.J, R)), rng.standard_normal((R, R))
+    for k in range(X.K):
+        Q, w, loss = O.project(Xs[k], V, H, n_steps=10)
+        Qb, wb, lb = _project_bruteforce(Xs[k].toarray(), V, H, 10)
+        np.testing.assert_allclose(w, wb, rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(Q, Qb, rtol=1e-10, atol=1e-12)
+        assert abs(loss - lb) <= 1e-10 * max(lb, 1.0)
+
+
+def test_procrustes_economy_when_fewer_rows_than_rank():
+    # I_k < R: the thin SVD has I_k singular values; Q_k has orthonormal rows
+    # and attains tr(Q^T B) = ||B||_* over all matrices with orthonormal rows
+    rng = np.random.default_rng(14)
+    I, J, R = 3, 9, 5
+    Xd = rng.random((I, J))
+    H = rng.standard_normal((R, R))
+    w = 0.5 + rng.random(R)
+    V = rng.random((J, R))
+    Q = O.procrustes_q(sp.csr_matrix(Xd), H, w, V)
+    B = Xd @ V @ np.diag(w) @ H.T
+    assert Q.shape == (I, R)
+    np.testing.assert_allclose(Q @ Q.T, np.eye(I), atol=1e-13)
+    nuc = np.linalg.svd(B, compute_uv=False).sum()
+    assert abs(np.trace(Q.T @ B) - nuc) <= 1e-12 * nuc
+    for _ in range(100):
+        Qp = _rand_orth(rng, R, I).T  # orthonormal rows
+        assert np.trace(Qp.T @ B) <= nuc + 1e-12
+    # and it is the economy polar factor B (B^T B)^{+1/2} on B's row space
+    lam, E = np.linalg.eigh(B.T @ B)
+    keep = lam > 1e-12 * lam.max()
+    Gm = (E[:, keep] / np.sqrt(lam[keep])) @ E[:, keep].T
+    np.testing.assert_allclose(Q, B @ Gm, atol=1e-11)
+
+
+def test_economy_subjects_keep_the_loss_monotone():
+    # subjects with I_k < R mixed with taller ones: the ALS objective still
+    # never increases (each step minimises it over its own block)
+    X = gen_slices(30, 12, (1, 8), _poisson_plus_one(3.0), "uniform", [4713])
+    assert (X.I() < 4).any()
+    Xs = _xs(X)
+    H, V, W = gen_init(X.J, X.K, 4, [4713, 1])
+    _, _, _, hist = O.run(Xs, H, V, W, 25, dense_loss=True)
+    losses = [h["loss"] for h in hist]
+    for a, b in zip(losses, losses[1:]):
+        assert b <= a * (1 + 1e-12)
+    # the dense loss and the expanded formula (which assumes Q_k^T Q_k = I)
+    # differ once some Q_k has orthonormal rows only: the oracle's dense loss
+    # is the objective itself
+    Hn, Vn, Wn, info = O.iterate(Xs, H, V, W, dense_loss=True)
+    assert info["loss"] >= 0.0
+
+
+def test_run_until_stops_on_the_relative_loss_change():
+    X, R = gen_config(1)
+    Xs = _xs(X)
+    H, V, W = gen_init(X.J, X.K, R, [170304219, 1, 1])
+    tol = 1e-3
+    _, _, _, hist = O.run_until(Xs, H, V, W, 200, tol)
+    _, _, _, full = O.run(Xs, H, V, W, len(hist) + 1, dense_loss=False)
+    losses = [h["loss"] for h in full]
+    n = len(hist)
+    assert 2 <= n < 200
+    # the same iterates as a plain run of that length
+    np.testing.assert_allclose([h["loss"] for h in hist], losses[:n], rtol=1e-12)
+    # the criterion holds at the stop and at no earlier iteration
+    rel = [abs(a - b) / a for a, b in zip(losses, losses[1:])]
+    assert rel[n - 2] <= tol
+    assert all(r > tol for r in rel[:n - 2])
+
+
+def test_u_factors_reconstruct_the_model():
+    # U_k S_k V^T equals Q_k H S_k V^T (Sec. "Model"), and U_k^T U_k = H^T H
+    # is the same for every subject (the PARAFAC2 constraint)
+    X, R = _small(K=6, J=10, R=3, seed=95)
+    Xs = _xs(X)
+    H, V, W = _state(X, R, 95)
+    H1, V1, W1, info = O.iterate(Xs, H, V, W)
+    Us = O.u_factors(info["Q"], H1)
+    for k in range(X.K):
+        np.testing.assert_allclose(Us[k] @ np.diag(W1[k]) @ V1.T,
+                                   info["Q"][k] @ H1 @ np.diag(W1[k]) @ V1.T, atol=1e-13)
+        np.testing.assert_allclose(Us[k].T @ Us[k], H1.T @ H1, atol=1e-12)
