@@ -192,12 +192,21 @@ def replay(server, t, reqs, stop_after: float):
     return done
 
 
+def _flush(server):
+    """Finish every queued and in-flight request and drop the results."""
+    server.drain()
+    while any(server.pending()):
+        server.poll()
+        server.drain()
+
+
 def _trace(server, t, reqs, warm: float, span: float) -> dict:
     """Replay arrivals t (seconds, from 0) for warm + span seconds; latency of
     each request arriving after warm = completion time - scheduled arrival."""
     m = int(np.searchsorted(t, warm + span))
+    _flush(server)
     done = replay(server, t[:m], reqs[:m], stop_after=warm + span + 5.0)
-    server.drain()
+    _flush(server)  # requests left over when the window closed
     lat = done - t[:m]
     sel = t[:m] >= warm
     ok = np.isfinite(lat) & sel

@@ -601,3 +601,4 @@ def parafac2_server_create(model: Model, **opts) -> Server:
 def parafac2_project(model: Model, X: DeviceSlices, n_steps: int = 10, w0=None,
                      want_q: bool = True, stream=None):
     return model.project(X, n_steps, w0, want_q, stream)
+

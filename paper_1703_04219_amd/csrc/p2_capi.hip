@@ -1212,6 +1212,53 @@ int parafac2_model_workspace_size(int64_t J, int32_t R, size_t* bytes) {
   return P2_OK;
 }
 
+// Enqueue the model state into m->ws on stream s: V (J x R) copied into rows
+// of LDV floats, H, V^T V, H^T H, N3 = (V^T V) * (H^T H) and N3^+.  No
+// allocation and no synchronisation.
+static hipError_t model_fill(parafac2_model* m, const float* V, const double* H, hipStream_t s) {
+  const int64_t J = m->J;
+  const int R = m->R;
+  float* Vm = reinterpret_cast<float*>(m->ws + m->oV);
+  double* Hm = reinterpret_cast<double*>(m->ws + m->oH);
+  double* VtV = reinterpret_cast<double*>(m->ws + m->oVtV);
+  int32_t* map = reinterpret_cast<int32_t*>(m->ws + m->oMap);
+  hipError_t e;
+  if ((e = p2::run_fill_f32(Vm, J * m->LDV, 0.f, s)) != hipSuccess) return e;
+  if ((e = p2::run_iota(map, J, s)) != hipSuccess) return e;
+  if ((e = p2::run_permute_rows(V, Vm, J, R, R, m->LDV, map, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(Hm, H, sizeof(double) * R * R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return e;
+  if ((e = p2::run_fill_f64(VtV, (int64_t)R * R, 0.0, s)) != hipSuccess) return e;
+  if ((e = p2::run_gram_rows(R, Vm, J, m->LDV, VtV, s)) != hipSuccess) return e;
+  return p2::run_model_prep(R, VtV, Hm, reinterpret_cast<double*>(m->ws + m->oHtH),
+                            reinterpret_cast<double*>(m->ws + m->oN3),
+                            reinterpret_cast<double*>(m->ws + m->oN3p), m->pp, s);
+}
+
+// Checks of a projection request against model m (shapes and pointers).
+static int check_request(const parafac2_model* m, const parafac2_csr* req, int32_t n_steps,
+                         const float* w_out) {
+  if (!req || !w_out) return fail(P2_EINVAL, "NULL argument");
+  if (req->J != m->J) return fail(P2_EINVAL, "request J=%lld != model J=%lld",
+                                  (long long)req->J, (long long)m->J);
+  if (req->K < 0 || n_steps < 0) return fail(P2_EINVAL, "bad sizes");
+  if (req->K > 0 && (!req->subj_ptr || !req->row_ptr || (req->nnz > 0 && (!req->col || !req->val))))
+    return fail(P2_EINVAL, "NULL array");
+  return P2_OK;
+}
+
+static int project_launch(const parafac2_model* m, const parafac2_csr* req, int32_t n_steps,
+                          const float* w0, float* Q_out, float* w_out, double* loss_out,
+                          hipStream_t s) {
+  p2::XRaw X{req->subj_ptr, req->row_ptr, req->col, req->val};
+  HIP_TRY(p2::run_project(m->R, X, req->K, reinterpret_cast<const float*>(m->ws + m->oV),
+                          reinterpret_cast<const double*>(m->ws + m->oH),
+                          reinterpret_cast<const double*>(m->ws + m->oN3),
+                          reinterpret_cast<const double*>(m->ws + m->oN3p), n_steps, w0, Q_out,
+                          w_out, loss_out, m->pp, s));
+  return P2_OK;
+}
+
 int parafac2_model_create(parafac2_model** out, int64_t J, int32_t R, const float* V,
                           const double* H, void* workspace, size_t ws_bytes, void* stream) {
   if (!out) return fail(P2_EINVAL, "out is NULL");
@@ -1233,49 +1280,23 @@ int parafac2_model_create(parafac2_model** out, int64_t J, int32_t R, const floa
     delete m;
     return fail(P2_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   }
-  hipStream_t s = m->stream;
-  float* Vm = reinterpret_cast<float*>(m->ws + m->oV);
-  double* Hm = reinterpret_cast<double*>(m->ws + m->oH);
-  double* VtV = reinterpret_cast<double*>(m->ws + m->oVtV);
-  int32_t* map = reinterpret_cast<int32_t*>(m->ws + m->oMap);
-  auto bad = [&](hipError_t e, const char* what) {
+  hipError_t e = model_fill(m, V, H, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) {
     delete m;
-    return fail(P2_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-  };
-  hipError_t e;
-  if ((e = p2::run_fill_f32(Vm, J * m->LDV, 0.f, s)) != hipSuccess) return bad(e, "fill");
-  if ((e = p2::run_iota(map, J, s)) != hipSuccess) return bad(e, "iota");
-  if ((e = p2::run_permute_rows(V, Vm, J, R, R, m->LDV, map, s)) != hipSuccess) return bad(e, "copy V");
-  if ((e = hipMemcpyAsync(Hm, H, sizeof(double) * R * R, hipMemcpyDeviceToDevice, s)) != hipSuccess)
-    return bad(e, "copy H");
-  if ((e = p2::run_fill_f64(VtV, (int64_t)R * R, 0.0, s)) != hipSuccess) return bad(e, "fill");
-  if ((e = p2::run_gram_rows(R, Vm, J, m->LDV, VtV, s)) != hipSuccess) return bad(e, "VtV");
-  if ((e = p2::run_model_prep(R, VtV, Hm, reinterpret_cast<double*>(m->ws + m->oHtH),
-                              reinterpret_cast<double*>(m->ws + m->oN3),
-                              reinterpret_cast<double*>(m->ws + m->oN3p), m->pp, s)) != hipSuccess)
-    return bad(e, "N3");
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "sync");
+    return fail(P2_EDEVICE, "model state: %s", hipGetErrorString(e));
+  }
   *out = m;
   return P2_OK;
 }
 
 int parafac2_project(parafac2_model* m, const parafac2_csr* req, int32_t n_steps, const float* w0,
                      float* Q_out, float* w_out, double* loss_out, void* stream) {
-  if (!m || !req || !w_out) return fail(P2_EINVAL, "NULL argument");
-  if (req->J != m->J) return fail(P2_EINVAL, "request J=%lld != model J=%lld",
-                                  (long long)req->J, (long long)m->J);
-  if (req->K < 0 || n_steps < 0) return fail(P2_EINVAL, "bad sizes");
+  if (!m) return fail(P2_EINVAL, "NULL argument");
+  P2_TRY(check_request(m, req, n_steps, w_out));
   if (req->K == 0) return P2_OK;
-  if (!req->subj_ptr || !req->row_ptr || (req->nnz > 0 && (!req->col || !req->val)))
-    return fail(P2_EINVAL, "NULL array");
   hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : m->stream;
-  p2::XRaw X{req->subj_ptr, req->row_ptr, req->col, req->val};
-  HIP_TRY(p2::run_project(m->R, X, req->K, reinterpret_cast<const float*>(m->ws + m->oV),
-                          reinterpret_cast<const double*>(m->ws + m->oH),
-                          reinterpret_cast<const double*>(m->ws + m->oN3),
-                          reinterpret_cast<const double*>(m->ws + m->oN3p), n_steps, w0, Q_out,
-                          w_out, loss_out, m->pp, s));
-  return P2_OK;
+  return project_launch(m, req, n_steps, w0, Q_out, w_out, loss_out, s);
 }
 
 void parafac2_model_destroy(parafac2_model* m) { delete m; }
