@@ -97,6 +97,79 @@ def pinv_sym(N):
     return (E * inv) @ E.T
 
 
+def nnls_normal(N, m, max_outer=None):
+    """min_{x >= 0} ||y - Z x||^2 given only N = Z^T Z (symmetric positive
+    definite, R x R) and m = Z^T y: the active-set method of Lawson and
+    Hanson in the form that works on the cross products (the fast NNLS of Bro
+    and De Jong, which the paper uses for the non-negative S_k and V, Sec.
+    "Setup").  P is the passive set (free variables), the others are held at
+    zero.
+      x = 0, w = m - N x
+      while some j outside P has w_j > tol:
+          move the j with the largest w_j into P
+          s = solution of N[P,P] s_P = m_P, s = 0 outside P
+          while some s_j <= 0 on P:
+              step x towards s as far as x stays >= 0 (alpha = min over
+              those j of x_j / (x_j - s_j)); variables that reach 0 leave P;
+              solve again on the new P
+          x = s, w = m - N x
+    tol is 10 R eps times the scale of m and N x."""
+    N = np.asarray(N, np.float64)
+    m = np.asarray(m, np.float64)
+    R = m.shape[0]
+    eps = EPS64
+    x = np.zeros(R)
+    P = np.zeros(R, dtype=bool)
+    max_outer = 3 * R if max_outer is None else max_outer
+
+    def solve(Pm):
+        s = np.zeros(R)
+        idx = np.nonzero(Pm)[0]
+        if idx.size:
+            s[idx] = np.linalg.solve(N[np.ix_(idx, idx)], m[idx])
+        return s
+
+    scale = max(float(np.max(np.abs(m))), np.finfo(np.float64).tiny)
+    tol = 10.0 * R * eps * scale
+    w = m - N @ x
+    blocked = np.zeros(R, dtype=bool)  # entered and left again without a step
+    for _ in range(max_outer):
+        cand = np.where(~P & ~blocked, w, -np.inf)
+        j = int(np.argmax(cand))
+        if not (cand[j] > tol):
+            break
+        P[j] = True
+        s = solve(P)
+        for _ in range(R + 1):
+            bad = np.nonzero(P & (s <= 0))[0]
+            if bad.size == 0:
+                break
+            d = x[bad] - s[bad]
+            ratio = np.where(d > 0, x[bad] / np.where(d > 0, d, 1.0), 0.0)
+            q = int(np.argmin(ratio))
+            alpha = ratio[q]
+            x = x + alpha * (s - x)
+            x[bad[q]] = 0.0  # the variable that limits the step reaches zero
+            P &= ~(x <= 10.0 * eps * max(float(np.max(np.abs(x))), 1e-300))
+            x[~P] = 0.0
+            if alpha > 0:
+                blocked[:] = False
+            elif not P[j]:
+                blocked[j] = True  # rounding: w_j > tol but its solve was <= 0
+            s = solve(P)
+        x = s
+        w = m - N @ x
+        scale = max(scale, float(np.max(np.abs(N @ x))))
+        tol = 10.0 * R * eps * scale
+    return x
+
+
+def nnls_rows(N, M):
+    """Row by row: X(i, :) = argmin over x >= 0 of the least-squares problem
+    with normal equations N x = M(i, :) (nnls_normal)."""
+    return np.array([nnls_normal(N, M[i]) for i in range(M.shape[0])]).reshape(M.shape)
+
+
 def procrustes_q(X, H, w, V):
     """Q-step for one subject (Sec. "Classical Algorithm for PARAFAC2",
     objective (procrustes_obj)): SVD of H S_k V^T X_k^T = P diag(s) Z^T,
@@ -234,9 +307,13 @@ def loss_expanded(nx2, M3, W, V, H):
     return nx2 - 2.0 * float(np.sum(W * M3)) + float(np.sum((W @ N3) * W))
 
 
-def iterate(Xs, H, V, W, nx2=None, dense_loss=True, normalize=True):
+def iterate(Xs, H, V, W, nx2=None, dense_loss=True, normalize=True, nonneg=False):
     """One PARAFAC2-ALS iteration (Algorithm "PARAFAC2-ALS" body: Q-step,
     build {Y_k}, one CP-ALS iteration (Algorithm "CP-ALS"), S_k <- diag(W(k,:))).
+    nonneg: V and W (the diagonals of S_k) are updated by non-negative least
+    squares on the same normal equations (the constraints of the paper's
+    experiments, Sec. "Classical Algorithm for PARAFAC2" and Sec. "Setup");
+    H stays unconstrained.
     Returns the new (H, V, W) and a dict with Q, Y, M1, M2, M3, loss, fit."""
     R = H.shape[0]
     if nx2 is None:
@@ -250,12 +327,14 @@ def iterate(Xs, H, V, W, nx2=None, dense_loss=True, normalize=True):
         H1 = normalize_cols(H1)
     # mode 2: V <- Y_(2)(W (.) H)(W^T W * H^T H)^+, normalise
     M2 = mttkrp(Ys, H1, V, W, 2)
-    V1 = M2 @ pinv_sym((W.T @ W) * (H1.T @ H1))
+    N2 = (W.T @ W) * (H1.T @ H1)
+    V1 = nnls_rows(N2, M2) if nonneg else M2 @ pinv_sym(N2)
     if normalize:
         V1 = normalize_cols(V1)
     # mode 3: W <- Y_(3)(V (.) H)(V^T V * H^T H)^+
     M3 = mttkrp(Ys, H1, V1, W, 3)
-    W1 = M3 @ pinv_sym((V1.T @ V1) * (H1.T @ H1))
+    N3 = (V1.T @ V1) * (H1.T @ H1)
+    W1 = nnls_rows(N3, M3) if nonneg else M3 @ pinv_sym(N3)
     if dense_loss:
         loss = loss_dense(Xs, Qs, H1, V1, W1)
     else:
@@ -264,13 +343,13 @@ def iterate(Xs, H, V, W, nx2=None, dense_loss=True, normalize=True):
 
 
 
-def run(Xs, H, V, W, n_iter, dense_loss=True):
+def run(Xs, H, V, W, n_iter, dense_loss=True, nonneg=False):
     """n_iter iterations from (H, V, W); returns the final state and the list
     of per-iteration info dicts."""
     nx2 = norm_x_sq(Xs)
     hist = []
     for _ in range(n_iter):
-        H, V, W, info = iterate(Xs, H, V, W, nx2, dense_loss)
+        H, V, W, info = iterate(Xs, H, V, W, nx2, dense_loss, nonneg=nonneg)
         hist.append(info)
     return H, V, W, hist
 

@@ -492,3 +492,63 @@ def test_u_factors_reconstruct_the_model():
         np.testing.assert_allclose(Us[k] @ np.diag(W1[k]) @ V1.T,
                                    info["Q"][k] @ H1 @ np.diag(W1[k]) @ V1.T, atol=1e-13)
         np.testing.assert_allclose(Us[k].T @ Us[k], H1.T @ H1, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# N1: non-negative least squares on the normal equations (V and S_k >= 0)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(8))
+def test_nnls_normal_matches_scipy_and_kkt(seed):
+    # min_{x >= 0} ||y - Z x|| from (Z^T Z, Z^T y) against scipy's NNLS on Z, y
+    # itself, and the KKT conditions: x >= 0, gradient w = m - N x <= 0 where
+    # x = 0 and = 0 where x > 0
+    from scipy.optimize import nnls
+    rng = np.random.default_rng(500 + seed)
+    n, R = 30, [3, 5, 10, 16][seed % 4]
+    Z = rng.standard_normal((n, R)) + (0.5 if seed % 2 else 0.0)
+    y = rng.standard_normal(n)
+    N, m = Z.T @ Z, Z.T @ y
+    x = O.nnls_normal(N, m)
+    xs, _ = nnls(Z, y)
+    np.testing.assert_allclose(x, xs, rtol=1e-9, atol=1e-11)
+    assert np.all(x >= 0)
+    w = m - N @ x
+    scale = np.abs(m).max()
+    assert np.all(w[x == 0] <= 1e-10 * scale)
+    assert np.all(np.abs(w[x > 0]) <= 1e-10 * scale)
+    # an unconstrained minimiser that is already >= 0 is returned as is
+    yp = Z @ (0.5 + rng.random(R))
+    np.testing.assert_allclose(O.nnls_normal(N, Z.T @ yp), np.linalg.solve(N, Z.T @ yp),
+                               rtol=1e-9)
+    # m <= 0 everywhere with N having non-negative entries: x = 0
+    Zp = np.abs(Z)
+    assert not np.any(O.nnls_normal(Zp.T @ Zp, -np.abs(Zp.T @ y)))
+
+
+def test_nonnegative_iteration_keeps_factors_nonnegative_and_loss_monotone():
+    # the constrained ALS: V and W stay >= 0, the objective never increases,
+    # and each V and W row is the NNLS solution of its normal equations
+    X, R = gen_config(1)
+    Xs = _xs(X)
+    H, V, W = _state(X, R, 17)  # Gaussian H: unconstrained updates go negative
+    H1, V1, W1, info = O.iterate(Xs, H, V, W, nonneg=True)
+    assert np.all(V1 >= 0) and np.all(W1 >= 0)
+    assert (V1 == 0).any()  # the constraint binds on V
+    Hu, Vu, Wu, _ = O.iterate(Xs, H, V, W)
+    assert (Vu < 0).any()
+    N2 = (W.T @ W) * (H1.T @ H1)
+    # V rows before the column normalisation: the KKT conditions of each row
+    # with a zero (gradient <= 0 at the zeros, = 0 on the support), and the
+    # same zero pattern as the normalised V
+    for j in np.nonzero((V1 == 0).any(axis=1))[0][:5]:
+        v = O.nnls_normal(N2, info["M2"][j])
+        np.testing.assert_array_equal(v == 0, V1[j] == 0)
+        g = info["M2"][j] - N2 @ v
+        assert np.all(v >= 0)
+        assert np.all(g[v == 0] <= 1e-9 * max(np.abs(info["M2"][j]).max(), 1e-300))
+        assert np.all(np.abs(g[v > 0]) <= 1e-9 * max(np.abs(info["M2"][j]).max(), 1e-300))
+    _, _, _, hist = O.run(Xs, H, V, W, 15, dense_loss=True, nonneg=True)
+    losses = [h["loss"] for h in hist]
+    for a, b in zip(losses, losses[1:]):
+        assert b <= a * (1 + 1e-12)
