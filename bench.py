@@ -36,7 +36,7 @@ def parse():
                    help="1-3 one decomposition; 4 the 64-problem batch; 5 the serving trace")
     p.add_argument("--k-limit", type=int, default=None, help="only the first K subjects")
     p.add_argument("--cpu-subjects", type=int, default=-1,
-                   help="subjects in the oracle's timed sample (0 = skip; default: 200,000 "
+                   help="subjects in the oracle's timed sample (0 = skip; default: 500,000 "
                         "at R=10 and 20,000 at R=40, 10-20 s on 16 host cores)")
     p.add_argument("--profile-only", action="store_true",
                    help="skip the CPU baseline (for profiler runs)")
@@ -506,7 +506,7 @@ def main():
     cpu = None
     if a.cpu_subjects and not a.profile_only:
         print("[bench] timing the oracle on a sample ...", file=sys.stderr, flush=True)
-        n_cpu = a.cpu_subjects if a.cpu_subjects > 0 else {1: X.K, 2: 200000, 3: 20000}[a.config]
+        n_cpu = a.cpu_subjects if a.cpu_subjects > 0 else {1: X.K, 2: 500000, 3: 50000}[a.config]
         cpu = cpu_baseline(X, R, a.config, n_cpu)
         print(f"[bench] oracle: {cpu['value']:.3e} nnz/s on {cpu['cores']} workers",
               file=sys.stderr, flush=True)
