@@ -328,6 +328,25 @@ int parafac2_project(parafac2_model* m, const parafac2_csr* req, int32_t n_steps
 
 void parafac2_model_destroy(parafac2_model* m);
 
+/* parafac2_project for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same projection as parafac2_model_create + parafac2_project, with the
+ * model state (V in rows of R rounded up to 4 floats, H, (V^T V) * (H^T H)
+ * and its pseudo-inverse) built on the stream in a device scratch array of
+ * the library instead of a caller workspace.  The scratch holds at most
+ * 8 MiB of model state: J * ceil4(R) * 4 + 6 * R * R * 8 + 4 * J bytes (plus
+ * 256-byte alignment of each part), e.g. J <= 50,000 at R = 40; larger J or R
+ * gives P2_EINVAL.  Nothing is allocated and nothing is synchronised.  V, H,
+ * req, w0, Q_out, w_out and loss_out are as for parafac2_model_create and
+ * parafac2_project (device); stream as elsewhere (NULL = default stream).
+ * Each device has one scratch array, shared by every call on it and left
+ * holding the last call's model state: calls that overlap on one device
+ * (other streams, other threads) race and give wrong results; serialise
+ * them on one stream. */
+int parafac2_project_noalloc(int64_t J, int32_t R, const float* V, const double* H,
+                             const parafac2_csr* req, int32_t n_steps, const float* w0,
+                             float* Q_out, float* w_out, double* loss_out, void* stream);
+
 /* ---- serving: continuous batching of projection requests ------------------
  * A server projects requests (single new subjects, each an I x J slice in
  * host memory) onto a model as they arrive.  Requests wait in a bounded host

@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
         "parafac2_model_create": (ctypes.c_int, [P(vp), i64, i32, vp, vp, vp, sz, vp]),
         "parafac2_project": (ctypes.c_int, [vp, P(Csr), i32, vp, vp, vp, vp, vp]),
         "parafac2_model_destroy": (None, [vp]),
+        "parafac2_project_noalloc": (ctypes.c_int, [i64, i32, vp, vp, P(Csr), i32, vp, vp, vp,
+                                                    vp, vp]),
         "parafac2_set_sched": (ctypes.c_int, [vp, P(Sched)]),
         "parafac2_autotune": (ctypes.c_int, [vp, i32, P(Sched), P(ctypes.c_double)]),
         "parafac2_batch_workspace_size": (ctypes.c_int, [P(vp), i32, P(sz)]),
@@ -128,7 +130,7 @@ def exported_symbols() -> list:
             "parafac2_get_u", "parafac2_set_profiling",
             "parafac2_get_profile", "parafac2_launch_config", "parafac2_destroy",
             "parafac2_model_workspace_size", "parafac2_model_create", "parafac2_project",
-            "parafac2_model_destroy", "parafac2_set_sched", "parafac2_autotune",
+            "parafac2_model_destroy", "parafac2_project_noalloc", "parafac2_set_sched", "parafac2_autotune",
             "parafac2_batch_workspace_size", "parafac2_batch_create", "parafac2_batch_iterate",
             "parafac2_batch_set_sched", "parafac2_batch_autotune", "parafac2_batch_set_profiling",
             "parafac2_batch_get_profile", "parafac2_batch_destroy",
@@ -602,3 +604,15 @@ def parafac2_project(model: Model, X: DeviceSlices, n_steps: int = 10, w0=None,
                      want_q: bool = True, stream=None):
     return model.project(X, n_steps, w0, want_q, stream)
 
+
+def parafac2_project_noalloc(V, H, X: DeviceSlices, n_steps: int = 10, w0=None, out=None,
+                             stream=None):
+    """Projection with the model state in the library's device scratch (no
+    workspace); V (J x R float32) and H (R x R float64) are device tensors and
+    out = (Q, w, loss) device tensors of the right shapes (Q may be None)."""
+    Q, w, loss = out
+    csr = X.csr()
+    _check(load().parafac2_project_noalloc(int(V.shape[0]), int(V.shape[1]), _ptr(V), _ptr(H),
+                                           ctypes.byref(csr), n_steps, _ptr(w0), _ptr(Q),
+                                           _ptr(w), _ptr(loss), _stream_handle(stream)))
+    return Q, w, loss

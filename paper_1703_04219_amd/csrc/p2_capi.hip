@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -827,6 +828,36 @@ static int validate_host_impl(const parafac2_csr* X, int32_t R, std::string& msg
   return P2_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Device scratch of parafac2_project_noalloc: the model state of one call
+// (padded V, H, V^T V, H^T H, N3, N3^+, row map), at most kNoAllocScratchBytes.
+// Each device holds its own copy for the life of the process.  Host code
+// never uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+
+static int noalloc_scratch(void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};  // device -> address of its scratch copy
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(P2_ENOTSUP, "device %d: at most %d devices", dev,
+                                                 kMaxDevices);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(P2_EDEVICE, "no device address for the scratch array");
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return P2_OK;
+}
+
 extern "C" {
 
 int parafac2_abi_version(void) { return PARAFAC2_ABI_VERSION; }
@@ -1300,5 +1331,30 @@ int parafac2_project(parafac2_model* m, const parafac2_csr* req, int32_t n_steps
 }
 
 void parafac2_model_destroy(parafac2_model* m) { delete m; }
+
+int parafac2_project_noalloc(int64_t J, int32_t R, const float* V, const double* H,
+                             const parafac2_csr* req, int32_t n_steps, const float* w0,
+                             float* Q_out, float* w_out, double* loss_out, void* stream) {
+  if (!V || !H || J < 1 || R < 1) return fail(P2_EINVAL, "bad arguments");
+  if (!p2::rank_supported(R)) return fail(P2_ENOTSUP, "R=%d is not built", R);
+  parafac2_model m;  // on the stack: its state lives in the device scratch array
+  m.J = J;
+  m.R = R;
+  m.LDV = ldv_of(R);
+  m.pp = polar_params(nullptr, R);
+  model_layout(&m);
+  if (m.total > kNoAllocScratchBytes)
+    return fail(P2_EINVAL, "J=%lld, R=%d need %zu bytes of model state, more than the %zu bytes "
+                "of the no-allocation scratch", (long long)J, R, m.total, kNoAllocScratchBytes);
+  P2_TRY(check_request(&m, req, n_steps, w_out));
+  void* base = nullptr;
+  P2_TRY(noalloc_scratch(&base));
+  m.ws = reinterpret_cast<unsigned char*>(base);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const hipError_t e = model_fill(&m, V, H, s);
+  if (e != hipSuccess) return fail(P2_EDEVICE, "model state: %s", hipGetErrorString(e));
+  if (req->K == 0) return P2_OK;
+  return project_launch(&m, req, n_steps, w0, Q_out, w_out, loss_out, s);
+}
 
 }  // extern "C"
