@@ -128,7 +128,14 @@ typedef struct {
                             floats, R rounded up to even; ranks <= 20) so that
                             a schedule with warm_polar can start the next
                             eigen-solve from it; 0: no bases are kept          */
-  int32_t reserved[1];
+  int32_t nonneg;        /* 1: V and W (the diagonals of S_k) are updated by
+                            non-negative least squares on the same normal
+                            equations (the constraints of the paper's
+                            experiments, Sec. "Classical Algorithm for PARAFAC2"
+                            and Sec. "Setup"); H stays unconstrained.  The
+                            next Procrustes step is then not fused into the
+                            mode-3 pass (one more pass over X per iteration);
+                            0: unconstrained                                  */
 } parafac2_opts;
 
 /* ABI version of the loaded library (PARAFAC2_ABI_VERSION). */

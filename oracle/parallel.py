@@ -135,10 +135,11 @@ class Pool:
         singular values above cut * sigma_max (0 where B_k = 0)."""
         return np.concatenate(self._map("kappa", H0, V0, W0, (cut,)))
 
-    def iterate(self, H0, V0, W0, nx2=None):
+    def iterate(self, H0, V0, W0, nx2=None, nonneg=False):
         """One PARAFAC2-ALS iteration from (H0, V0, W0), as
-        parafac2_oracle.iterate with the expanded loss.  Returns
-        (H1, V1, W1, info) with info = M1, M2, M3, loss, fit, seconds."""
+        parafac2_oracle.iterate with the expanded loss (nonneg: V and W by
+        NNLS, in the parent).  Returns (H1, V1, W1, info) with info = M1, M2,
+        M3, loss, fit, seconds."""
         t0 = time.perf_counter()
         if nx2 is None:
             nx2 = self.norm_x_sq()
@@ -149,9 +150,11 @@ class Pool:
         M2 = np.zeros(V0.shape)
         for part in self._map("m2", H0, V0, W0, (H1,)):
             M2 += part
-        V1 = O.normalize_cols(M2 @ O.pinv_sym((W0.T @ W0) * (H1.T @ H1)))
+        N2 = (W0.T @ W0) * (H1.T @ H1)
+        V1 = O.normalize_cols(O.nnls_rows(N2, M2) if nonneg else M2 @ O.pinv_sym(N2))
         M3 = np.concatenate(self._map("m3", H0, V0, W0, (H1, V1)))
-        W1 = M3 @ O.pinv_sym((V1.T @ V1) * (H1.T @ H1))
+        N3 = (V1.T @ V1) * (H1.T @ H1)
+        W1 = O.nnls_rows(N3, M3) if nonneg else M3 @ O.pinv_sym(N3)
         loss = O.loss_expanded(nx2, M3, W1, V1, H1)
         return H1, V1, W1, dict(M1=M1, M2=M2, M3=M3, loss=loss, fit=1.0 - loss / nx2,
                                 nx2=nx2, seconds=time.perf_counter() - t0)

@@ -88,9 +88,10 @@ int64_t mode2_parts(int64_t K, int R, int cap) {
 
 // Offsets of every piece of the context workspace.
 struct Plan {
-  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, order, V[2], F, M2, M3, E, small, err,
-      part, desc, tiles, m2tiles, tickets, iter, total;
+  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, order, V[2], F, M2, M3, M3d, E, small,
+      err, part, desc, tiles, m2tiles, tickets, iter, total;
   bool warm = false;
+  bool nonneg = false;  // V and W by NNLS: a float64 copy of M3 feeds the W rows
   int64_t cap_tiles = 0, cap_m2 = 0;  // tile capacities of the context's own runner
   int m2cap = 0;                      // mode-2 partial-sum slots
   int hot = 0;
@@ -124,6 +125,8 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const p
   p.F = take(sizeof(double) * (size_t)K * R * R);
   p.M2 = take(sizeof(float) * J * LDV);
   p.M3 = take(sizeof(float) * (size_t)K * R);
+  p.nonneg = o && o->nonneg;
+  p.M3d = p.nonneg ? take(sizeof(double) * (size_t)K * R) : 0;
   p.warm = (o && o->keep_bases) && p2::warm_supported(R);
   const int64_t NC = (R & 1) ? R + 1 : R;
   p.E = p.warm ? take(sizeof(float) * (size_t)K * NC * R) : 0;
@@ -231,6 +234,8 @@ struct parafac2_ctx {
     d.nparts = 0;  // set by the runner from its schedule
     d.hot = hot;
     d.order = at<int32_t>(plan.order);
+    d.M3d = plan.nonneg ? at<double>(plan.M3d) : nullptr;
+    d.nonneg = plan.nonneg ? 1 : 0;
     return d;
   }
 };
@@ -243,6 +248,7 @@ namespace {
 
 struct Group {
   int R = 0;
+  bool nonneg = false;  // some member updates V and W by NNLS
   std::vector<int> members;  // indices into Runner::ctxs
   p2::PolarParams pp{};
   p2::BatchView bv{};
@@ -261,6 +267,7 @@ struct Runner {
   hipStream_t cap = nullptr;  // capture stream of the graphs
   hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   bool planned = false;
+  bool any_nonneg = false;
   // profiling: event pairs per phase, resolved lazily
   bool profiling = false;
   struct EvPair {
@@ -462,11 +469,13 @@ int runner_body(Runner& r, int parity, int do_next, hipStream_t s, bool prof) {
     // mode 2 -> V
     PHASE(P2_PHASE_MODE2, HIP_TRY(p2::run_mode2(b, parity, s)));
     PHASE(P2_PHASE_VUPDATE, HIP_TRY(p2::run_vupdate(b, parity, s));
+          if (g.nonneg) HIP_TRY(p2::run_nnls(b, 0, parity, s));
           HIP_TRY(p2::run_gram(b, 1, parity, s)); HIP_TRY(p2::run_solve_n3(b, g.pp, s));
           HIP_TRY(p2::run_vscale(b, parity, s)));
     // mode 3 -> W, fit (+ next Procrustes step)
     if (do_next) HIP_TRY(p2::run_zero(b, 1, s));
-    PHASE(P2_PHASE_GAMMA, HIP_TRY(p2::run_gamma(b, parity, do_next, g.pp, s)));
+    PHASE(P2_PHASE_GAMMA, HIP_TRY(p2::run_gamma(b, parity, do_next, g.pp, s));
+          if (g.nonneg) HIP_TRY(p2::run_nnls(b, 1, parity, s)));
     PHASE(P2_PHASE_FIT, HIP_TRY(p2::run_fit(b, s)));
   }
   return P2_OK;
@@ -510,7 +519,9 @@ int runner_iterate_n(Runner& r, int32_t n, double* fit_host, double* loss_host) 
   int qv = -1;
   for (int32_t it = 0; it < n; ++it) {
     if (!have_F) P2_TRY(runner_alpha(r, parity, s, prof));
-    const int do_next = (it + 1 < n) ? 1 : 0;
+    // the non-negative W rows are solved after the mode-3 pass, so the next
+    // Procrustes step cannot be fused into it
+    const int do_next = (it + 1 < n && !r.any_nonneg) ? 1 : 0;
     if (graph) {
       if (!r.exec[parity][do_next]) P2_TRY(runner_capture(r, parity, do_next));
       HIP_TRY(hipGraphLaunch(r.exec[parity][do_next], s));
@@ -742,6 +753,8 @@ int runner_make(Runner** out, parafac2_ctx* const* ctxs, int n, const RunnerLayo
     g.tickets = reinterpret_cast<int*>(base + lg.tickets);
     g.cap_tiles = lg.cap_tiles;
     g.cap_m2 = lg.cap_m2;
+    for (int i : lg.members) g.nonneg = g.nonneg || ctxs[i]->plan.nonneg;
+    r->any_nonneg = r->any_nonneg || g.nonneg;
     r->groups.push_back(g);
   }
   *out = r;

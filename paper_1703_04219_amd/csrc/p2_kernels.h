@@ -69,6 +69,9 @@ hipError_t run_mode2(const BatchView& b, int parity, hipStream_t s);
 hipError_t run_gram(const BatchView& b, int which, int parity, hipStream_t s);
 hipError_t run_solve_h(const BatchView& b, const PolarParams& pp, hipStream_t s);
 hipError_t run_vupdate(const BatchView& b, int parity, hipStream_t s);
+// Non-negative rows of the problems with the constraint: which = 0 V_{t+1}
+// (instead of run_vupdate), 1 W with the fit terms (after run_gamma).
+hipError_t run_nnls(const BatchView& b, int which, int parity, hipStream_t s);
 hipError_t run_solve_n3(const BatchView& b, const PolarParams& pp, hipStream_t s);
 hipError_t run_vscale(const BatchView& b, int parity, hipStream_t s);
 // Zero per-problem accumulators: 1 M1, 2 W^T W, 4 V^T V raw, 8 fit terms, 16 M2.

@@ -288,6 +288,7 @@ __global__ void __launch_bounds__(256, PolarLds<R>::kMinWaves) k_gamma(const Pro
     float* __restrict__ W = D.W;
     double* __restrict__ F = D.F;
     float* __restrict__ M3 = D.M3;
+    double* __restrict__ M3d = D.nonneg ? D.M3d : nullptr;
     __syncthreads();
     load_shared_rxr<R>(Hs, D.H);
     load_shared_rxr<R>(N3s, D.small + SL.N3);
@@ -343,9 +344,11 @@ __global__ void __launch_bounds__(256, PolarLds<R>::kMinWaves) k_gamma(const Pro
           glob(W)[k * R + c] = (float)wn;
           glob(M3)[k * R + c] = (float)m3;
           wv[c] = (double)(float)wn;
+          // the non-negative W update (k_nnls_rows) starts from the float64 row
+          if (M3d) glob(M3d)[k * R + c] = m3;
         }
         wave_sync();
-        if (real) {
+        if (real && !M3d) {
           const double wf = wv[c];
           double tt = 0.0;
 #pragma unroll
@@ -832,6 +835,7 @@ __global__ void __launch_bounds__(256) k_vupdate(const ProbDesc* __restrict__ P,
   constexpr int LDV = Geo<R>::LDV;
   constexpr SmallLayout SL = small_layout(R);
   const ProbDesc& D = P[blockIdx.y];
+  if (D.nonneg) return;  // k_nnls_rows updates V
   const P2_GLOBAL float* M2 = glob(D.M2);
   const P2_GLOBAL double* N2p = glob(D.small) + SL.N2p;
   P2_GLOBAL float* Vout = glob(D.V[parity ^ 1]);
@@ -846,6 +850,259 @@ __global__ void __launch_bounds__(256) k_vupdate(const ProbDesc* __restrict__ P,
 #pragma unroll
       for (int l = 0; l < R; ++l) t = fma(m[l], N2p[l * R + c], t);
       Vout[j * LDV + c] = (float)t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Non-negative least squares per row: the non-negative V and S_k of the
+// paper's experiments (Sec. "Classical Algorithm for PARAFAC2" and Sec.
+// "Setup", where the fast NNLS of Bro and De Jong is used).  For one row m of
+// an MTTKRP and the R x R normal matrix N of its update, x = argmin over
+// x >= 0 of the least-squares problem whose normal equations are N x = m, by
+// the active-set method on the cross products N, m:
+//   x = 0; w = m - N x
+//   while the largest w_j off the passive set P exceeds tol: j joins P;
+//     s = solution of N[P,P] s_P = m_P (0 off P);
+//     while some s_j <= 0 on P: step x towards s until the first such x_j
+//       reaches 0, drop the variables at 0 from P, solve again;
+//     x = s; w = m - N x.
+// One group of NC lanes per row, lane c owns x_c and column c of N (N is
+// symmetric).  Reductions over the group (largest gradient, smallest step,
+// largest |x|) go through LDS and take the first index on ties.  The passive
+// block is solved by a Cholesky factorisation of N with the rows and columns
+// off P replaced by those of the identity, column c per lane, factor columns
+// broadcast through LDS.
+// ---------------------------------------------------------------------------
+template <int R>
+struct NnlsLds {
+  static constexpr int NC = Geo<R>::NC;
+  // L (R x R, factor column k at k * R), v (R), xs (NC), pf (NC), red (NC)
+  static constexpr int kPerGroup = R * R + R + 3 * NC;
+};
+
+// Group reductions over lanes 0..R-1 of one value per lane: largest value
+// (first index on ties) or smallest value (first index on ties).
+template <int R>
+__device__ __forceinline__ void group_argmax(double* red, double v, int c, double& best, int& at) {
+  if (c < R) red[c] = v;
+  wave_sync();
+  best = red[0];
+  at = 0;
+  for (int i = 1; i < R; ++i) {
+    const double t = red[i];
+    if (t > best) {
+      best = t;
+      at = i;
+    }
+  }
+  wave_sync();
+}
+
+template <int R>
+__device__ __forceinline__ void group_argmin(double* red, double v, int c, double& best, int& at) {
+  if (c < R) red[c] = v;
+  wave_sync();
+  best = red[0];
+  at = 0;
+  for (int i = 1; i < R; ++i) {
+    const double t = red[i];
+    if (t < best) {
+      best = t;
+      at = i;
+    }
+  }
+  wave_sync();
+}
+
+// s_c of the solution of N[P,P] s_P = m_P (s = 0 off P) for the group.
+template <int R>
+__device__ double nnls_solve(const double (&ncol)[R], double m, bool p, int c, double* L,
+                             double* v, double* pf) {
+  const bool real = c < R;
+  if (real) pf[c] = p ? 1.0 : 0.0;
+  wave_sync();
+  double g[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) g[i] = (p && pf[i] != 0.0) ? ncol[i] : (i == c ? 1.0 : 0.0);
+#pragma nounroll
+  for (int k = 0; k < R; ++k) {
+    if (c == k) {
+      const double piv = g[k];
+      const double rs = piv > 0.0 ? 1.0 / sqrt(piv) : 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        g[i] *= rs;
+        L[k * R + i] = g[i];
+      }
+    }
+    wave_sync();
+    if (real && c > k) {
+      const double lck = L[k * R + c];
+#pragma unroll
+      for (int i = 0; i < R; ++i) g[i] = fma(-lck, L[k * R + i], g[i]);
+    }
+    wave_sync();
+  }
+  if (real) v[c] = p ? m : 0.0;
+  wave_sync();
+#pragma nounroll
+  for (int k = 0; k < R; ++k) {  // L y = m_P
+    if (c == k) {
+      const double d = L[k * R + k];
+      v[k] = d > 0.0 ? v[k] / d : 0.0;
+    }
+    wave_sync();
+    if (real && c > k) v[c] = fma(-L[k * R + c], v[k], v[c]);
+    wave_sync();
+  }
+#pragma nounroll
+  for (int k = R - 1; k >= 0; --k) {  // L^T s = y
+    if (c == k) {
+      const double d = L[k * R + k];
+      v[k] = d > 0.0 ? v[k] / d : 0.0;
+    }
+    wave_sync();
+    if (real && c < k) v[c] = fma(-L[c * R + k], v[k], v[c]);
+    wave_sync();
+  }
+  const double sc = (real && p) ? v[c] : 0.0;
+  wave_sync();
+  return sc;
+}
+
+// x_c of the NNLS solution for the group's row (m = m_c of lane c).
+template <int R>
+__device__ double nnls_group(const double (&ncol)[R], double m, int c, double* buf) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr double eps = 2.220446049250313e-16;
+  const double inf = __builtin_huge_val();
+  double* L = buf;
+  double* v = L + R * R;
+  double* xs = v + R;
+  double* pf = xs + NC;
+  double* red = pf + NC;
+  const bool real = c < R;
+  double x = 0.0;
+  bool p = false, blocked = false;
+  double scale, tmp;
+  int at;
+  group_argmax<R>(red, real ? fabs(m) : 0.0, c, scale, at);
+  scale = fmax(scale, 2.2250738585072014e-308);
+  double tol = 10.0 * R * eps * scale;
+  double w = m;
+  for (int outer = 0; outer < 3 * R; ++outer) {
+    double best;
+    int j;
+    group_argmax<R>(red, (real && !p && !blocked) ? w : -inf, c, best, j);
+    if (!(best > tol)) break;
+    if (c == j) p = true;
+    double s = nnls_solve<R>(ncol, m, p, c, L, v, pf);
+    for (int inner = 0; inner <= R; ++inner) {
+      const bool bad = p && s <= 0.0;
+      const double d = x - s;
+      double alpha;
+      int q;
+      group_argmin<R>(red, bad ? (d > 0.0 ? x / d : 0.0) : inf, c, alpha, q);
+      if (alpha == inf) break;
+      x = fma(alpha, s - x, x);
+      if (c == q) x = 0.0;  // the variable that limits the step reaches zero
+      double xm;
+      group_argmax<R>(red, real ? fabs(x) : 0.0, c, xm, at);
+      if (p && x <= 10.0 * eps * fmax(xm, 1e-300)) p = false;
+      if (!p) x = 0.0;
+      if (alpha > 0.0)
+        blocked = false;
+      else if (c == j && !p)
+        blocked = true;  // rounding: w_j > tol but its solve was <= 0
+      s = nnls_solve<R>(ncol, m, p, c, L, v, pf);
+    }
+    x = s;
+    if (real) xs[c] = x;
+    wave_sync();
+    double nx = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) nx = fma(ncol[i], xs[i], nx);
+    wave_sync();
+    w = m - nx;
+    group_argmax<R>(red, real ? fabs(nx) : 0.0, c, tmp, at);
+    scale = fmax(scale, tmp);
+    tol = 10.0 * R * eps * scale;
+  }
+  return x;
+}
+
+// which = 0: V_{t+1} rows = NNLS((W^T W) * (H^T H), M2 rows) (replaces
+// k_vupdate); which = 1: W rows = NNLS(N3, M3 rows, from the float64 copy of
+// M3), and the fit terms <W, M3> and W N3 W^T.  Problems without the
+// constraint are skipped.  grid.y = problem.
+template <int R>
+__global__ void __launch_bounds__(256) k_nnls_rows(const ProbDesc* __restrict__ P, int which,
+                                                    int parity) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int GPW = Geo<R>::GPW;
+  constexpr int LDV = Geo<R>::LDV;
+  constexpr SmallLayout SL = small_layout(R);
+  const ProbDesc& D = P[blockIdx.y];
+  if (!D.nonneg) return;
+  double* Ns = reinterpret_cast<double*>(p2_smem);  // N (R x R), then the fit partials
+  double* shFit = Ns + R * R;
+  const Lane L = lane_info<R>();
+  const int wave = threadIdx.x / kWave;
+  const int gpb = (blockDim.x / kWave) * GPW;
+  double* buf = shFit + 2 + (wave * GPW + (L.live ? L.grp : 0)) * NnlsLds<R>::kPerGroup;
+  const P2_GLOBAL double* sm = glob(D.small);
+  for (int q = threadIdx.x; q < R * R; q += blockDim.x)
+    Ns[q] = which == 0 ? sm[SL.WtW + q] * sm[SL.HtH + q] : sm[SL.N3 + q];
+  if (threadIdx.x < 2) shFit[threadIdx.x] = 0.0;
+  __syncthreads();
+  const int c = L.j;
+  const bool real = c < R;
+  const int cc = real ? c : 0;
+  double ncol[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) ncol[i] = Ns[i * R + cc];
+  const int64_t n = which == 0 ? D.J : D.K;
+  double fa = 0.0, fb = 0.0;
+  if (L.live) {
+    const int64_t stride = (int64_t)gridDim.x * gpb;
+    for (int64_t r = (int64_t)blockIdx.x * gpb + wave * GPW + L.grp; r < n; r += stride) {
+      const double m = !real ? 0.0
+                       : which == 0 ? (double)glob(D.M2)[r * LDV + c]
+                                    : glob(D.M3d)[r * R + c];
+      const double x = nnls_group<R>(ncol, m, c, buf);
+      if (which == 0) {
+        if (real) glob(D.V[parity ^ 1])[r * LDV + c] = (float)x;
+      } else {
+        // fit terms from the stored (float) W row, as in the unconstrained path
+        const double xf = (double)(float)x;
+        double* xs = buf + R * R + R;
+        if (real) {
+          glob(D.W)[r * R + c] = (float)x;
+          glob(D.M3)[r * R + c] = (float)m;
+          xs[c] = xf;
+        }
+        wave_sync();
+        double nx = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) nx = fma(ncol[i], xs[i], nx);
+        wave_sync();
+        if (real) {
+          fa = fma(xf, m, fa);
+          fb = fma(xf, nx, fb);
+        }
+      }
+    }
+  }
+  if (which == 1) {
+    if (L.live && real) {
+      atomicAdd(&shFit[0], fa);
+      atomicAdd(&shFit[1], fb);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      gadd(D.small + SL.fitacc + 0, shFit[0]);
+      gadd(D.small + SL.fitacc + 1, shFit[1]);
     }
   }
 }
@@ -1832,6 +2089,24 @@ hipError_t run_vupdate(const BatchView& b, int parity, hipStream_t s) {
   P2_DISPATCH(b.R, hipLaunchKernelGGL(k_vupdate<RR>, dim3(grid1(b.maxJ), b.np), dim3(256), 0, s,
                                       b.desc, parity);
               return hipGetLastError())
+}
+
+template <int R>
+hipError_t nnls_t(const BatchView& b, int which, int parity, hipStream_t s) {
+  constexpr int T = 256;
+  constexpr int gpb = (T / kWave) * Geo<R>::GPW;
+  constexpr size_t lds = sizeof(double) * (R * R + 2 + gpb * NnlsLds<R>::kPerGroup);
+  static_assert(lds <= kLdsBudget, "NNLS LDS plan");
+  hipError_t e = allow_lds(k_nnls_rows<R>, lds);
+  if (e != hipSuccess) return e;
+  const int64_t rows = which == 0 ? b.maxJ : b.maxK;
+  const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((rows + gpb - 1) / gpb, 8192));
+  hipLaunchKernelGGL(k_nnls_rows<R>, dim3(gx, b.np), dim3(T), lds, s, b.desc, which, parity);
+  return hipGetLastError();
+}
+
+hipError_t run_nnls(const BatchView& b, int which, int parity, hipStream_t s) {
+  P2_DISPATCH(b.R, return nnls_t<RR>(b, which, parity, s))
 }
 
 hipError_t run_solve_n3(const BatchView& b, const PolarParams& pp, hipStream_t s) {
