@@ -345,7 +345,7 @@ def batched(specs, Xs, steps: int, warmup: int, autotune: bool) -> dict:
 
 
 def decomposition(X, R: int, cfg: int, steps: int, warmup: int, autotune: bool,
-                  sched=None, traffic_file=None) -> dict:
+                  sched=None, traffic_file=None, nonneg=False) -> dict:
     """Time `steps` ALS iterations of one decomposition after `warmup`, with the
     library's per-launch HIP events on the context's stream; returns the
     iteration time, the phases and the roofline of the Procrustes/mode-3
@@ -358,7 +358,7 @@ def decomposition(X, R: int, cfg: int, steps: int, warmup: int, autotune: bool,
     torch.cuda.reset_peak_memory_stats()
     base = torch.cuda.memory_allocated()
     dX = B.DeviceSlices.from_slices(X)
-    opts = B.make_opts(sched=sched) if sched is not None else None
+    opts = B.make_opts(sched=sched, nonneg=nonneg) if (sched is not None or nonneg) else None
     ctx = B.Context(dX, R, H0, V0, W0, opts)
     del dX  # the context re-encoded the input into its workspace
     torch.cuda.synchronize()
@@ -486,13 +486,14 @@ def main():
     X, R = gen_config(a.config, k_limit=a.k_limit)
     print(f"[bench] generated K={X.K} J={X.J} R={R} rows={X.n_rows} nnz={X.nnz} "
           f"in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    X3 = specs = Xb = None
+    X3 = specs = Xb = shaped = None
     if extras:
         t0 = time.perf_counter()
         X3, _ = gen_config(3)
         print(f"[bench] generated the R=40 workload, nnz={X3.nnz}, in "
               f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
         specs, Xb = gen_batch_inputs()
+        shaped = {cfg: gen_config(cfg)[0] for cfg in (6, 7)}
     import torch
 
     from paper_1703_04219_amd import binding as B
@@ -522,6 +523,18 @@ def main():
         dec3["roofline"] = roofline_of(dec3, copy_gbps)
         more["r40"] = dec3
         del X3
+        # the paper's timed setting: non-negative V and S_k (NNLS rows)
+        nn = decomposition(X, R, a.config, a.steps, 1, False, nonneg=True)
+        more["r10_nonneg"] = {k: nn[k] for k in ("ms_per_step", "nnz_per_s", "fit_after",
+                                                 "phase_ms_per_launch", "kernels")}
+        # workloads shaped like the paper's EHR and ratings data, at R = 10 and 40
+        for cfg, Xs_ in shaped.items():
+            for r in (10, 40):
+                d = decomposition(Xs_, r, cfg, a.steps, 1, False)
+                more[f"{CONFIGS[cfg]['name'].rsplit('_R', 1)[0]}_R{r}"] = {
+                    k: d[k] for k in ("K", "J", "R", "nnz", "ms_per_step", "nnz_per_s",
+                                      "fit_after", "phase_ms_per_launch")}
+        del shaped
         more["batched"] = batched(specs, Xb, a.steps, a.warmup, not a.no_autotune)
         del Xb
         more["serving"] = serving(a)

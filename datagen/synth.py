@@ -119,16 +119,22 @@ def _gpu_runtime_started() -> bool:
 
 def _gen_chunk(args):
     """One chunk of subjects (runs in a worker process for large inputs)."""
-    (child, nk, take, J, ik_range, nnz_row, col_dist, zipf_s, perm_seed) = args
+    (child, nk, take, J, ik_range, nnz_row, col_dist, zipf_s, perm_seed, ik_draw, val_draw) = args
     draw = make_col_sampler(J, col_dist, zipf_s, perm_seed=perm_seed)
     rng = np.random.default_rng(child)
-    Ik = rng.integers(ik_range[0], ik_range[1] + 1, size=nk, dtype=np.int64)
+    if ik_draw is None:
+        Ik = rng.integers(ik_range[0], ik_range[1] + 1, size=nk, dtype=np.int64)
+    else:
+        Ik = np.asarray(ik_draw(rng, nk), dtype=np.int64)
     nr = int(Ik.sum())
     rl = np.asarray(nnz_row(rng, nr), dtype=np.int64)
     np.clip(rl, 1, J, out=rl)
     row_id = np.repeat(np.arange(nr, dtype=np.int64), rl)
     cols = _distinct_sorted_rows(rng, row_id, J, draw)
-    vals = (1.0 - rng.random(cols.shape[0])).astype(np.float32)
+    if val_draw is None:
+        vals = (1.0 - rng.random(cols.shape[0])).astype(np.float32)
+    else:
+        vals = np.asarray(val_draw(rng, cols.shape[0]), dtype=np.float32)
     if take < nk:
         nr_t = int(Ik[:take].sum())
         nz_t = int(rl[:nr_t].sum())
@@ -147,6 +153,8 @@ def gen_slices(
     chunk: int = CHUNK,
     k_limit: Optional[int] = None,
     workers: Optional[int] = None,
+    ik_draw=None,
+    val_draw=None,
 ) -> Slices:
     """Generate K slices chunk by chunk.  seed is a sequence of ints; chunk c uses
     child c of SeedSequence(seed); the column permutation uses seed + [2].
@@ -161,7 +169,8 @@ def gen_slices(
     for c in range((k_stop + chunk - 1) // chunk):
         nk = min(chunk, K - c * chunk)
         take = min(nk, k_stop - c * chunk)
-        jobs.append((children[c], nk, take, J, ik_range, nnz_row, col_dist, zipf_s, perm_seed))
+        jobs.append((children[c], nk, take, J, ik_range, nnz_row, col_dist, zipf_s, perm_seed,
+                     ik_draw, val_draw))
     if workers is None:
         workers = min(16, os.cpu_count() or 1) if len(jobs) >= 8 else 1
         if _gpu_runtime_started():
@@ -193,6 +202,24 @@ class _poisson_plus_one:
         return 1 + rng.poisson(self.lam, size=n)
 
 
+class _geometric_rows:
+    """lo + Geometric(p) - 1 rows, truncated at hi (many subjects with few
+    observations, a long tail of frequent ones)."""
+
+    def __init__(self, lo, hi, p):
+        self.lo, self.hi, self.p = lo, hi, p
+
+    def __call__(self, rng, n):
+        return np.minimum(self.lo - 1 + rng.geometric(self.p, size=n), self.hi)
+
+
+class _half_stars:
+    """Values in {0.5, 1.0, ..., 5.0}, uniform (rating-like)."""
+
+    def __call__(self, rng, n):
+        return 0.5 * rng.integers(1, 11, size=n)
+
+
 class _uniform_int:
     """Uniform integer count in [lo, hi]."""
 
@@ -216,6 +243,18 @@ CONFIGS = {
     # scaled to ~490M nnz, R=40
     3: dict(name="c3_K1M_J5000_R40_490Mnnz", K=1_000_000, J=5000, R=40, ik=(40, 100),
             nnz_row=("poisson1", 6.0), cols="zipf"),
+    # the shape of the paper's EHR data (Table "table:data_stats": 464,900
+    # subjects, 1,328 variables, at most 166 observations, 12.3M nonzeros):
+    # I_k = 2 + Geometric(1/7) - 1 truncated at 166 (mean about 8), 1 +
+    # Poisson(2.3) codes per weekly observation at Zipf(1.1) columns
+    6: dict(name="c6_ehr_like_K465K_J1328_R10", K=464_900, J=1328, R=10, ik=(2, 166),
+            ik_draw=("geometric", 2, 166, 1.0 / 7.0), nnz_row=("poisson1", 2.3), cols="zipf"),
+    # the shape of the paper's ratings data (25,249 users, 26,096 movies, at
+    # most 19 yearly observations, 8.9M nonzeros): I_k uniform in [2, 19],
+    # 1 + Poisson(32.5) ratings per year at Zipf(1.1) columns, values in
+    # half stars
+    7: dict(name="c7_ratings_like_K25K_J26096_R10", K=25_249, J=26_096, R=10, ik=(2, 19),
+            nnz_row=("poisson1", 32.5), cols="zipf", vals="half_stars"),
 }
 
 
@@ -229,11 +268,17 @@ def _nnz_sampler(spec):
 
 
 def gen_config(cfg: int, k_limit: Optional[int] = None) -> tuple[Slices, int]:
-    """Slices of configuration cfg (1..3), optionally only the first k_limit
+    """Slices of configuration cfg (1..3, 6, 7), optionally only the first k_limit
     subjects (identical to the leading subjects of the full input)."""
     c = CONFIGS[cfg]
+    ik_draw = None
+    if "ik_draw" in c:
+        kind, lo, hi, p = c["ik_draw"]
+        assert kind == "geometric"
+        ik_draw = _geometric_rows(lo, hi, p)
+    val_draw = _half_stars() if c.get("vals") == "half_stars" else None
     X = gen_slices(c["K"], c["J"], c["ik"], _nnz_sampler(c["nnz_row"]), c["cols"],
-                   [ROOT_SEED, cfg], k_limit=k_limit)
+                   [ROOT_SEED, cfg], k_limit=k_limit, ik_draw=ik_draw, val_draw=val_draw)
     return X, c["R"]
 
 

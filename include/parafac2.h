@@ -64,9 +64,13 @@ typedef struct parafac2_model parafac2_model;
  * strictly increasing within a row; values are finite.  Empty rows are
  * accepted (they contribute nothing; the paper filters them, Sec.
  * "Challenges of PARAFAC2 on sparse data").  Limits of the library:
- * I_k >= R (the rank-R Procrustes factor with orthonormal columns needs
- * I_k >= R), I_k <= 65535, nnz of one subject <= 65535, J <= 65536,
- * K <= 2^31 - 1. */
+ * 1 <= I_k <= 65535, nnz of one subject <= 65535, J <= 65536,
+ * K <= 2^31 - 1.  A subject with I_k < R (the paper runs such data at ranks
+ * above its largest I_k, Table "table:data_stats") gets the economy
+ * Procrustes factor Q_k = Z P^T from the thin SVD H S_k V^T X_k^T = P S Z^T:
+ * an I_k x R matrix with orthonormal rows (Q_k Q_k^T = I), and the loss
+ * counts ||Q_k H S_k V^T||_F with that Q_k.  A context with such subjects
+ * does not fuse the next Procrustes step into the mode-3 pass. */
 typedef struct {
   int64_t K, J, n_rows, nnz;
   const int64_t* subj_ptr; /* [K+1]      */
@@ -145,7 +149,7 @@ int parafac2_abi_version(void);
 const char* parafac2_last_error(void);
 
 /* Host-only validation of a CSR whose pointers are HOST memory: shapes,
- * monotone offsets, column range and order, finiteness, I_k >= R and the
+ * monotone offsets, column range and order, finiteness, I_k >= 1 and the
  * build limits above.  Writes a message to msg (if non-NULL).  Returns P2_OK,
  * P2_EINVAL or P2_ENOTSUP.  Touches no GPU. */
 int parafac2_validate_host(const parafac2_csr* host_X, int32_t R, char* msg, size_t msg_len);

@@ -27,7 +27,11 @@ Readings of points the paper leaves open (each is listed in the design notes):
 * Q-step SVD (garbled in the text): the SVD of the R x I_k matrix
   H S_k V^T X_k^T is written P diag(sigma) Z^T, and Q_k = Z P^T; the rank-R
   truncation is the thin SVD.  For I_k < R the thin SVD has I_k singular
-  values and Q_k (I_k x R) has orthonormal rows instead of columns.
+  values and Q_k (I_k x R) has orthonormal rows instead of columns; there
+  the truncation also drops singular values at or below 10^-6.5 sigma_max
+  (numerically zero: rows of X_k that are multiples of each other), because
+  with orthonormal rows ||Q_k H S_k V^T|| and so the loss would depend on the
+  arbitrary completion of the missing directions.
 * Normalisation (Algorithm "CP-ALS", "Normalize columns"): H and V get unit
   2-norm columns after their updates and the norms are dropped; W is not
   normalised (S_k = diag(W(k,:)) carries the scale, Sec. "CP Decomposition").
@@ -184,6 +188,9 @@ def procrustes_q(X, H, w, V):
         # nothing (Y_k = 0) rather than an arbitrary orthonormal completion
         return np.zeros((X.shape[0], H.shape[0]))
     P, s, Zt = np.linalg.svd(M, full_matrices=False)
+    if X.shape[0] < H.shape[0]:
+        keep = s > s[0] * 10.0 ** -6.5
+        P, Zt = P[:, keep], Zt[keep]
     return Zt.T @ P.T
 
 

@@ -73,6 +73,11 @@ def _task(args):
         return O.mttkrp(Ys, extra[0], V0, W0r, 2)
     if kind == "m3":
         return O.mttkrp(Ys, extra[0], extra[1], W0r, 3)
+    if kind == "dloss":
+        # sum_k ||X_k - Q_k H1 S1_k V1^T||_F^2 over the range, densely
+        H1, V1, W1 = extra
+        Qs = [O.procrustes_q(Xk, H0, W0r[k], V0) for k, Xk in enumerate(Xs)]
+        return O.loss_dense(Xs, Qs, H1, V1, W1[k0:k1])
     if kind == "kappa":
         # condition number of B_k = X_k V S_k H^T at the input state, over the
         # singular values above cut * sigma_max (0 for B_k = 0)
@@ -135,11 +140,12 @@ class Pool:
         singular values above cut * sigma_max (0 where B_k = 0)."""
         return np.concatenate(self._map("kappa", H0, V0, W0, (cut,)))
 
-    def iterate(self, H0, V0, W0, nx2=None, nonneg=False):
+    def iterate(self, H0, V0, W0, nx2=None, nonneg=False, dense_loss=False):
         """One PARAFAC2-ALS iteration from (H0, V0, W0), as
-        parafac2_oracle.iterate with the expanded loss (nonneg: V and W by
-        NNLS, in the parent).  Returns (H1, V1, W1, info) with info = M1, M2,
-        M3, loss, fit, seconds."""
+        parafac2_oracle.iterate (nonneg: V and W by NNLS, in the parent;
+        dense_loss: the loss from the dense residuals, else the expanded
+        formula, which assumes Q_k^T Q_k = I).  Returns (H1, V1, W1, info)
+        with info = M1, M2, M3, loss, fit, seconds."""
         t0 = time.perf_counter()
         if nx2 is None:
             nx2 = self.norm_x_sq()
@@ -155,6 +161,9 @@ class Pool:
         M3 = np.concatenate(self._map("m3", H0, V0, W0, (H1, V1)))
         N3 = (V1.T @ V1) * (H1.T @ H1)
         W1 = O.nnls_rows(N3, M3) if nonneg else M3 @ O.pinv_sym(N3)
-        loss = O.loss_expanded(nx2, M3, W1, V1, H1)
+        if dense_loss:
+            loss = float(sum(self._map("dloss", H0, V0, W0, (H1, V1, W1))))
+        else:
+            loss = O.loss_expanded(nx2, M3, W1, V1, H1)
         return H1, V1, W1, dict(M1=M1, M2=M2, M3=M3, loss=loss, fit=1.0 - loss / nx2,
                                 nx2=nx2, seconds=time.perf_counter() - t0)

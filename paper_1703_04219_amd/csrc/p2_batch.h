@@ -58,6 +58,8 @@ struct ProbDesc {
                          // nullptr for the natural order
   double* M3d;      // K x R float64 copy of M3 (rows for the non-negative W update), or nullptr
   int32_t nonneg;   // 1: V and W (the diagonals of S_k) are updated by NNLS
+  const int32_t* econ;  // the subjects with I_k < R (n_econ of them)
+  int64_t n_econ;
 };
 
 // Subject handled at position pos of a tile.  The order only changes which

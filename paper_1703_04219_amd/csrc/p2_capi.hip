@@ -88,8 +88,8 @@ int64_t mode2_parts(int64_t K, int R, int cap) {
 
 // Offsets of every piece of the context workspace.
 struct Plan {
-  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, order, V[2], F, M2, M3, M3d, E, small,
-      err, part, desc, tiles, m2tiles, tickets, iter, total;
+  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, order, econ, V[2], F, M2, M3, M3d, E,
+      small, err, part, desc, tiles, m2tiles, tickets, iter, total;
   bool warm = false;
   bool nonneg = false;  // V and W by NNLS: a float64 copy of M3 feeds the W rows
   int64_t cap_tiles = 0, cap_m2 = 0;  // tile capacities of the context's own runner
@@ -120,6 +120,7 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const p
   p.perm = take(sizeof(int32_t) * J);
   p.hist = take(sizeof(uint32_t) * J);
   p.order = take(sizeof(int32_t) * K);
+  p.econ = take(sizeof(int32_t) * K);
   p.V[0] = take(sizeof(float) * J * LDV);
   p.V[1] = take(sizeof(float) * J * LDV);
   p.F = take(sizeof(double) * (size_t)K * R * R);
@@ -208,6 +209,7 @@ struct parafac2_ctx {
   bool have_F = false;  // F/M1 hold the Procrustes step of the next iteration
   bool failed = false;
   int64_t iters_done = 0;
+  int64_t n_econ = 0;  // subjects with I_k < R (economy Procrustes factor)
   std::vector<int64_t> subj_host;
   Runner* own = nullptr;  // batch of one over this context
 
@@ -236,6 +238,8 @@ struct parafac2_ctx {
     d.order = at<int32_t>(plan.order);
     d.M3d = plan.nonneg ? at<double>(plan.M3d) : nullptr;
     d.nonneg = plan.nonneg ? 1 : 0;
+    d.econ = at<int32_t>(plan.econ);
+    d.n_econ = n_econ;
     return d;
   }
 };
@@ -249,6 +253,7 @@ namespace {
 struct Group {
   int R = 0;
   bool nonneg = false;  // some member updates V and W by NNLS
+  bool econ = false;    // some member has subjects with I_k < R
   std::vector<int> members;  // indices into Runner::ctxs
   p2::PolarParams pp{};
   p2::BatchView bv{};
@@ -268,6 +273,7 @@ struct Runner {
   hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   bool planned = false;
   bool any_nonneg = false;
+  bool any_econ = false;
   // profiling: event pairs per phase, resolved lazily
   bool profiling = false;
   struct EvPair {
@@ -361,7 +367,7 @@ int runner_plan(Runner& r) {
     std::vector<p2::ProbDesc> descs;
     std::vector<p2::Tile> seq, m2seq;
     int max_hot = 0;
-    int64_t maxK = 0, maxJ = 0;
+    int64_t maxK = 0, maxJ = 0, maxEcon = 0;
     bool warm = r.sched.warm_polar != 0;
     for (size_t q = 0; q < g.members.size(); ++q) {
       parafac2_ctx* c = r.ctxs[g.members[q]];
@@ -382,6 +388,7 @@ int runner_plan(Runner& r) {
       warm = warm && c->plan.warm;
       maxK = std::max(maxK, c->K);
       maxJ = std::max(maxJ, c->J);
+      maxEcon = std::max(maxEcon, c->n_econ);
     }
     const std::vector<p2::Tile> tiles = bin_interleave(seq);
     const std::vector<p2::Tile> m2tiles = bin_interleave(m2seq);
@@ -412,6 +419,7 @@ int runner_plan(Runner& r) {
     b.m2_blocks = r.sched.m2_blocks;
     b.maxK = maxK;
     b.maxJ = maxJ;
+    b.maxEcon = maxEcon;
     HIP_TRY(p2::plan_launch(b));
   }
   r.planned = true;
@@ -475,7 +483,8 @@ int runner_body(Runner& r, int parity, int do_next, hipStream_t s, bool prof) {
     // mode 3 -> W, fit (+ next Procrustes step)
     if (do_next) HIP_TRY(p2::run_zero(b, 1, s));
     PHASE(P2_PHASE_GAMMA, HIP_TRY(p2::run_gamma(b, parity, do_next, g.pp, s));
-          if (g.nonneg) HIP_TRY(p2::run_nnls(b, 1, parity, s)));
+          if (g.nonneg) HIP_TRY(p2::run_nnls(b, 1, parity, s));
+          if (g.econ) HIP_TRY(p2::run_econ_fit(b, parity, s)));
     PHASE(P2_PHASE_FIT, HIP_TRY(p2::run_fit(b, s)));
   }
   return P2_OK;
@@ -519,9 +528,10 @@ int runner_iterate_n(Runner& r, int32_t n, double* fit_host, double* loss_host) 
   int qv = -1;
   for (int32_t it = 0; it < n; ++it) {
     if (!have_F) P2_TRY(runner_alpha(r, parity, s, prof));
-    // the non-negative W rows are solved after the mode-3 pass, so the next
-    // Procrustes step cannot be fused into it
-    const int do_next = (it + 1 < n && !r.any_nonneg) ? 1 : 0;
+    // the non-negative W rows are solved after the mode-3 pass, and the loss
+    // terms of subjects with I_k < R need this iteration's F_k after it, so
+    // in either case the next Procrustes step cannot be fused into that pass
+    const int do_next = (it + 1 < n && !r.any_nonneg && !r.any_econ) ? 1 : 0;
     if (graph) {
       if (!r.exec[parity][do_next]) P2_TRY(runner_capture(r, parity, do_next));
       HIP_TRY(hipGraphLaunch(r.exec[parity][do_next], s));
@@ -753,8 +763,12 @@ int runner_make(Runner** out, parafac2_ctx* const* ctxs, int n, const RunnerLayo
     g.tickets = reinterpret_cast<int*>(base + lg.tickets);
     g.cap_tiles = lg.cap_tiles;
     g.cap_m2 = lg.cap_m2;
-    for (int i : lg.members) g.nonneg = g.nonneg || ctxs[i]->plan.nonneg;
+    for (int i : lg.members) {
+      g.nonneg = g.nonneg || ctxs[i]->plan.nonneg;
+      g.econ = g.econ || ctxs[i]->n_econ > 0;
+    }
     r->any_nonneg = r->any_nonneg || g.nonneg;
+    r->any_econ = r->any_econ || g.econ;
     r->groups.push_back(g);
   }
   *out = r;
@@ -802,8 +816,8 @@ static int validate_host_impl(const parafac2_csr* X, int32_t R, std::string& msg
   for (int64_t k = 0; k < X->K; ++k) {
     const int64_t a = X->subj_ptr[k], b = X->subj_ptr[k + 1];
     if (b < a) { snprintf(buf, sizeof(buf), "subj_ptr decreases at subject %lld", (long long)k); msg = buf; return P2_EINVAL; }
-    if (b - a < R) {
-      snprintf(buf, sizeof(buf), "subject %lld has I_k=%lld < R=%d", (long long)k, (long long)(b - a), R);
+    if (b - a < 1) {
+      snprintf(buf, sizeof(buf), "subject %lld has no rows", (long long)k);
       msg = buf;
       return P2_EINVAL;
     }
@@ -908,7 +922,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   if (!p2::rank_supported(R)) return fail(P2_ENOTSUP, "R=%d is not built", R);
   if (X->J > 65536) return fail(P2_ENOTSUP, "J > 65536 is not supported");
   if (X->K > INT32_MAX) return fail(P2_ENOTSUP, "K > 2^31 - 1 is not supported");
-  if (X->n_rows < X->K * (int64_t)R) return fail(P2_EINVAL, "n_rows < K*R: some I_k < R");
+  if (X->n_rows < X->K) return fail(P2_EINVAL, "n_rows < K: some subject has no rows");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(P2_EINVAL, "workspace must be 256-byte aligned");
   const Plan plan = make_plan(X->K, X->J, X->n_rows, X->nnz, R, opts);
@@ -948,7 +962,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   } while (0)
   INIT_TRY(hipMemsetAsync(err, 0, sizeof(int) * 4, s));
   INIT_TRY(p2::run_validate(X->subj_ptr, X->row_ptr, X->col, X->val, X->K, X->n_rows, X->nnz,
-                            X->J, R, err, zbase, rbase, s));
+                            X->J, 1, err, zbase, rbase, s));
   int herr = 0;
   INIT_TRY(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
   INIT_TRY(hipStreamSynchronize(s));
@@ -957,7 +971,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
     if (herr & 2) return cleanup(fail(P2_EINVAL, "column index out of [0, J)"));
     if (herr & 4) return cleanup(fail(P2_EINVAL, "columns not strictly increasing within a row"));
     if (herr & 8) return cleanup(fail(P2_EINVAL, "non-finite value"));
-    if (herr & 32) return cleanup(fail(P2_EINVAL, "a subject has I_k < R=%d", R));
+    if (herr & 32) return cleanup(fail(P2_EINVAL, "a subject has no rows"));
     if (herr & 64) return cleanup(fail(P2_ENOTSUP, "a subject has more than 65535 rows"));
     if (herr & 128) return cleanup(fail(P2_ENOTSUP, "a subject has more than 65535 nonzeros"));
     return cleanup(fail(P2_EINVAL, "invalid input (code %d)", herr));
@@ -999,6 +1013,15 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   }
   INIT_TRY(hipMemcpyAsync(c->at<int32_t>(plan.order), order.data(), sizeof(int32_t) * X->K,
                           hipMemcpyHostToDevice, s));
+  // subjects with fewer rows than R get the economy Procrustes factor, whose
+  // loss terms need their own pass
+  std::vector<int32_t> econ;
+  for (int64_t k = 0; k < X->K; ++k)
+    if (c->subj_host[k + 1] - c->subj_host[k] < R) econ.push_back((int32_t)k);
+  c->n_econ = (int64_t)econ.size();
+  if (!econ.empty())
+    INIT_TRY(hipMemcpyAsync(c->at<int32_t>(plan.econ), econ.data(), sizeof(int32_t) * econ.size(),
+                            hipMemcpyHostToDevice, s));
   double* sm = c->small();
   const p2::SmallLayout SL = p2::small_layout(R);
   INIT_TRY(p2::run_fill_f64(sm, SL.total, 0.0, s));

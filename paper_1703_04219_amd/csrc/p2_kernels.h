@@ -44,6 +44,7 @@ struct BatchView {
                                    // plan_launch clears it for ranks built without it
   int max_hot = 0;                 // hot columns planned by the problems (max over them)
   int64_t maxK = 0, maxJ = 0;
+  int64_t maxEcon = 0;             // most subjects with I_k < R in one problem
   int m2_blocks = 0;               // mode-2 blocks meant to share a CU (0 = 1)
   int m2_threads = 0;              // in: requested mode-2 block size (0 = default); out: used
   // filled by plan_launch (needs the current device; nothing but launches
@@ -72,6 +73,8 @@ hipError_t run_vupdate(const BatchView& b, int parity, hipStream_t s);
 // Non-negative rows of the problems with the constraint: which = 0 V_{t+1}
 // (instead of run_vupdate), 1 W with the fit terms (after run_gamma).
 hipError_t run_nnls(const BatchView& b, int which, int parity, hipStream_t s);
+// Loss terms of the subjects with I_k < R (after the W update).
+hipError_t run_econ_fit(const BatchView& b, int parity, hipStream_t s);
 hipError_t run_solve_n3(const BatchView& b, const PolarParams& pp, hipStream_t s);
 hipError_t run_vscale(const BatchView& b, int parity, hipStream_t s);
 // Zero per-problem accumulators: 1 M1, 2 W^T W, 4 V^T V raw, 8 fit terms, 16 M2.

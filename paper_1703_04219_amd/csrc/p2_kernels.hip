@@ -1107,6 +1107,110 @@ __global__ void __launch_bounds__(256) k_nnls_rows(const ProbDesc* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Loss of subjects with I_k < R.  Their Procrustes factor Q_k = A F^T has
+// orthonormal rows (the economy polar factor), so Q_k^T Q_k is a projector P_k
+// rather than I and ||Q_k H S_k V^T||_F^2 = sum_rs w_r w_s (V^T V)_rs
+// (H^T P_k H)_rs instead of w^T ((V^T V) * (H^T H)) w, which the mode-3 pass
+// adds for every subject.  For each such subject this kernel forms
+// K = H^T P_k H = sum_i u_i^T u_i from the rows u_i = A(i, :) F^T H of U_k,
+// and adds the difference to the fit terms.  It runs after the W update
+// (w = the stored W_{t+1} row), with F_k still from this iteration's
+// Procrustes step (the next step is not fused for such problems).
+// grid.y = problem.
+// ---------------------------------------------------------------------------
+template <int R>
+struct EconLds {
+  static constexpr int NC = Geo<R>::NC;
+  static constexpr int CH = Geo<R>::CH;
+  // gathered rows (CH x R floats), U rows (CH x R doubles), w (R)
+  static constexpr int kPerGroup = (CH * R + 1) / 2 + CH * R + R;
+};
+
+template <int R>
+__global__ void __launch_bounds__(256) k_econ_fit(const ProbDesc* __restrict__ P, int parity) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr int GPW = Geo<R>::GPW;
+  constexpr int CH = Geo<R>::CH;
+  constexpr SmallLayout SL = small_layout(R);
+  const ProbDesc& D = P[blockIdx.y];
+  if (D.n_econ == 0) return;
+  double* VtVs = reinterpret_cast<double*>(p2_smem);
+  double* HtHs = VtVs + R * R;
+  double* Hs = HtHs + R * R;
+  double* shd = Hs + R * R;
+  const Lane L = lane_info<R>();
+  const int wave = threadIdx.x / kWave;
+  const int gpb = (blockDim.x / kWave) * GPW;
+  double* gb = shd + 2 + (wave * GPW + (L.live ? L.grp : 0)) * EconLds<R>::kPerGroup;
+  float* Ab = reinterpret_cast<float*>(gb);
+  double* Ub = gb + (CH * R + 1) / 2;
+  double* wv = Ub + CH * R;
+  load_shared_rxr<R>(VtVs, D.small + SL.VtV);
+  load_shared_rxr<R>(HtHs, D.small + SL.HtH);
+  load_shared_rxr<R>(Hs, D.H);
+  if (threadIdx.x == 0) shd[0] = 0.0;
+  __syncthreads();
+  const int c = L.j;
+  const bool real = c < R;
+  const int cc = real ? c : 0;
+  const float* __restrict__ V = D.V[parity];
+  double delta = 0.0;
+  if (L.live) {
+    for (int64_t e = (int64_t)blockIdx.x * gpb + wave * GPW + L.grp; e < D.n_econ;
+         e += (int64_t)gridDim.x * gpb) {
+      const int64_t k = glob(D.econ)[e];
+      const Subj sj = D.X.subj(k);
+      // T(:, c) = F^T H(:, c): T(q, c) = sum_p F(p, q) H(p, c), F(p, q) at q R + p
+      const P2_GLOBAL double* Fk = glob(D.F) + (size_t)k * R * R;
+      double fr[R], kc[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double t = 0.0;
+#pragma unroll
+        for (int p = 0; p < R; ++p) t = fma(Fk[q * R + p], Hs[p * R + cc], t);
+        fr[q] = t;
+        kc[q] = 0.0;
+      }
+      for (int i0 = 0; i0 < sj.nrows; i0 += CH) {
+        const int n = min(CH, sj.nrows - i0);
+        gather_rows<R>(D.X, sj, i0, n, V, Ab, c);
+        wave_sync();
+        if (real) {
+          for (int ii = 0; ii < n; ++ii) {
+            double u = 0.0;
+#pragma unroll
+            for (int q = 0; q < R; ++q) u = fma((double)Ab[ii * R + q], fr[q], u);
+            Ub[ii * R + c] = u;
+          }
+        }
+        wave_sync();
+        if (real) {
+          for (int ii = 0; ii < n; ++ii) {
+            const double uc = Ub[ii * R + c];
+#pragma unroll
+            for (int l = 0; l < R; ++l) kc[l] = fma(Ub[ii * R + l], uc, kc[l]);
+          }
+        }
+        wave_sync();
+      }
+      if (real) wv[c] = (double)glob(D.W)[k * R + c];
+      wave_sync();
+      if (real) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < R; ++l)
+          t = fma(wv[l] * VtVs[l * R + c], kc[l] - HtHs[l * R + c], t);
+        delta = fma(wv[c], t, delta);
+      }
+      wave_sync();
+    }
+  }
+  if (L.live && real && delta != 0.0) atomicAdd(&shd[0], delta);
+  __syncthreads();
+  if (threadIdx.x == 0 && shd[0] != 0.0) gadd(D.small + SL.fitacc + 1, shd[0]);
+}
+
 // Column norms of V_raw from its Gram, V^T V of the normalised V,
 // N3 = (V^T V) * (H^T H) and N3^+; grid = problems.
 template <int R>
@@ -2103,6 +2207,23 @@ hipError_t nnls_t(const BatchView& b, int which, int parity, hipStream_t s) {
   const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((rows + gpb - 1) / gpb, 8192));
   hipLaunchKernelGGL(k_nnls_rows<R>, dim3(gx, b.np), dim3(T), lds, s, b.desc, which, parity);
   return hipGetLastError();
+}
+
+template <int R>
+hipError_t econ_t(const BatchView& b, int parity, hipStream_t s) {
+  constexpr int T = 256;
+  constexpr int gpb = (T / kWave) * Geo<R>::GPW;
+  constexpr size_t lds = sizeof(double) * (3 * R * R + 2 + gpb * EconLds<R>::kPerGroup);
+  static_assert(lds <= kLdsBudget, "loss-correction LDS plan");
+  hipError_t e = allow_lds(k_econ_fit<R>, lds);
+  if (e != hipSuccess) return e;
+  const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((b.maxEcon + gpb - 1) / gpb, 4096));
+  hipLaunchKernelGGL(k_econ_fit<R>, dim3(gx, b.np), dim3(T), lds, s, b.desc, parity);
+  return hipGetLastError();
+}
+
+hipError_t run_econ_fit(const BatchView& b, int parity, hipStream_t s) {
+  P2_DISPATCH(b.R, return econ_t<RR>(b, parity, s))
 }
 
 hipError_t run_nnls(const BatchView& b, int which, int parity, hipStream_t s) {

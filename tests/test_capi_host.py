@@ -89,8 +89,13 @@ def test_validate_host_subject_count_limit():
 
 def test_validate_host_rank_rules():
     X, _ = gen_config(1)  # I_k in [5, 20]
-    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 6)
-    assert rc == B.P2_EINVAL and "I_k" in msg
+    # subjects with fewer rows than R are accepted (economy Procrustes factor)
+    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 40)
+    assert rc == B.P2_OK, msg
+    # a subject with no rows is not
+    sp = np.concatenate([[0], X.subj_ptr])
+    rc, msg = B.parafac2_validate_host(sp, X.row_ptr, X.col, X.val, X.J, 5)
+    assert rc == B.P2_EINVAL and "no rows" in msg
     rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 7)
     assert rc == B.P2_ENOTSUP
     rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 0)

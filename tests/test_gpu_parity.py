@@ -333,6 +333,9 @@ def test_invalid_input_is_rejected():
     with pytest.raises(B.Parafac2Error) as e:
         B.Context(dX, R, H0, V0, W0)
     assert e.value.code == B.P2_EINVAL
+    # a subject without rows (checked on the device during init)
+    sp = np.concatenate([[0], X.subj_ptr])
+    dX = B.DeviceSlices(sp, X.row_ptr, X.col, X.val, X.J)
     with pytest.raises(B.Parafac2Error) as e:
-        B.Context(B.DeviceSlices.from_slices(X), 6, np.eye(6), np.ones((X.J, 6)), np.ones((X.K, 6)))
-    assert e.value.code == B.P2_EINVAL
+        B.Context(dX, R, np.eye(R), np.ones((X.J, R)), np.ones((X.K + 1, R)))
+    assert e.value.code == B.P2_EINVAL and "no rows" in str(e.value)

@@ -552,3 +552,24 @@ def test_nonnegative_iteration_keeps_factors_nonnegative_and_loss_monotone():
     losses = [h["loss"] for h in hist]
     for a, b in zip(losses, losses[1:]):
         assert b <= a * (1 + 1e-12)
+
+
+def test_procrustes_economy_rank_deficient_keeps_the_row_space():
+    # I_k < R with two proportional rows: B has rank I_k - 1; the truncated
+    # factor maps onto range(B) only (Q Q^T = projector onto range(B), Q^T Q
+    # = projector onto the row space of B) and still attains ||B||_*
+    rng = np.random.default_rng(15)
+    R, J = 5, 8
+    x = rng.random(J)
+    Xd = np.vstack([x, 2.5 * x, rng.random(J)])
+    H = rng.standard_normal((R, R))
+    w = 0.5 + rng.random(R)
+    V = rng.random((J, R))
+    Q = O.procrustes_q(sp.csr_matrix(Xd), H, w, V)
+    B = Xd @ V @ np.diag(w) @ H.T
+    U, s, Vt = np.linalg.svd(B, full_matrices=False)
+    r = int((s > 1e-10 * s[0]).sum())
+    assert r == 2
+    np.testing.assert_allclose(Q @ Q.T, U[:, :r] @ U[:, :r].T, atol=1e-12)
+    np.testing.assert_allclose(Q.T @ Q, Vt[:r].T @ Vt[:r], atol=1e-12)
+    assert abs(np.trace(Q.T @ B) - s.sum()) <= 1e-12 * s.sum()
