@@ -971,9 +971,14 @@ __device__ double nnls_solve(const double (&ncol)[R], double m, bool p, int c, d
   return sc;
 }
 
-// x_c of the NNLS solution for the group's row (m = m_c of lane c).
+// x_c of the NNLS solution for the group's row (m = m_c of lane c).  warm:
+// lane c's variable was positive in the previous iteration's row; if solving
+// on that support gives a positive solution, the method starts from it (a
+// feasible point with x > 0 exactly on P, from which the steps above apply
+// unchanged), else from x = 0.  N is positive definite, so the solution is
+// unique and does not depend on the starting point.
 template <int R>
-__device__ double nnls_group(const double (&ncol)[R], double m, int c, double* buf) {
+__device__ double nnls_group(const double (&ncol)[R], double m, int c, double* buf, bool warm) {
   constexpr int NC = Geo<R>::NC;
   constexpr double eps = 2.220446049250313e-16;
   const double inf = __builtin_huge_val();
@@ -991,6 +996,28 @@ __device__ double nnls_group(const double (&ncol)[R], double m, int c, double* b
   scale = fmax(scale, 2.2250738585072014e-308);
   double tol = 10.0 * R * eps * scale;
   double w = m;
+  double any_warm;
+  group_argmax<R>(red, (real && warm) ? 1.0 : 0.0, c, any_warm, at);
+  if (any_warm > 0.0) {
+    const bool pw = real && warm;
+    const double s = nnls_solve<R>(ncol, m, pw, c, L, v, pf);
+    double smin;
+    group_argmin<R>(red, pw ? s : __builtin_huge_val(), c, smin, at);
+    if (smin > 0.0) {
+      p = pw;
+      x = s;
+      if (real) xs[c] = x;
+      wave_sync();
+      double nx = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) nx = fma(ncol[i], xs[i], nx);
+      wave_sync();
+      w = m - nx;
+      group_argmax<R>(red, real ? fabs(nx) : 0.0, c, tmp, at);
+      scale = fmax(scale, tmp);
+      tol = 10.0 * R * eps * scale;
+    }
+  }
   for (int outer = 0; outer < 3 * R; ++outer) {
     double best;
     int j;
@@ -1070,7 +1097,10 @@ __global__ void __launch_bounds__(256) k_nnls_rows(const ProbDesc* __restrict__ 
       const double m = !real ? 0.0
                        : which == 0 ? (double)glob(D.M2)[r * LDV + c]
                                     : glob(D.M3d)[r * R + c];
-      const double x = nnls_group<R>(ncol, m, c, buf);
+      // the previous iteration's row (V_t or W_t) gives the starting support
+      const bool warm = real && (which == 0 ? glob(D.V[parity])[r * LDV + c]
+                                            : glob(D.W)[r * R + c]) > 0.f;
+      const double x = nnls_group<R>(ncol, m, c, buf, warm);
       if (which == 0) {
         if (real) glob(D.V[parity ^ 1])[r * LDV + c] = (float)x;
       } else {
