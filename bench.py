@@ -345,7 +345,7 @@ def batched(specs, Xs, steps: int, warmup: int, autotune: bool) -> dict:
 
 
 def decomposition(X, R: int, cfg: int, steps: int, warmup: int, autotune: bool,
-                  sched=None, traffic_file=None, nonneg=False) -> dict:
+                  sched=None, traffic_file=None, nonneg=False, baseline=False) -> dict:
     """Time `steps` ALS iterations of one decomposition after `warmup`, with the
     library's per-launch HIP events on the context's stream; returns the
     iteration time, the phases and the roofline of the Procrustes/mode-3
@@ -358,7 +358,8 @@ def decomposition(X, R: int, cfg: int, steps: int, warmup: int, autotune: bool,
     torch.cuda.reset_peak_memory_stats()
     base = torch.cuda.memory_allocated()
     dX = B.DeviceSlices.from_slices(X)
-    opts = B.make_opts(sched=sched, nonneg=nonneg) if (sched is not None or nonneg) else None
+    opts = (B.make_opts(sched=sched, nonneg=nonneg, baseline=baseline)
+            if (sched is not None or nonneg or baseline) else None)
     ctx = B.Context(dX, R, H0, V0, W0, opts)
     del dX  # the context re-encoded the input into its workspace
     torch.cuda.synchronize()
@@ -522,7 +523,24 @@ def main():
         dec3["workload"] = CONFIGS[3]["name"]
         dec3["roofline"] = roofline_of(dec3, copy_gbps)
         more["r40"] = dec3
-        del X3
+        # the paper's comparison method ("Sparse PARAFAC2": explicit Y and a
+        # generic coordinate-format MTTKRP) on the same GPU: the R = 10
+        # workload whole, and the first 50,000 subjects of the R = 40 one
+        # next to SPARTan on the same subjects
+        from datagen import take_subjects
+        keep = ("ms_per_step", "nnz_per_s", "fit_after", "phase_ms_per_launch", "hbm_footprint")
+        bl = decomposition(X, R, a.config, 3, 1, False, baseline=True)
+        cmp = {"R10_full": {"baseline": {k: bl[k] for k in keep},
+                            "spartan_ms_per_step": dec["ms_per_step"],
+                            "spartan_speedup": bl["ms_per_step"] / dec["ms_per_step"]}}
+        X3s = take_subjects(X3, 0, 50000)
+        bl3 = decomposition(X3s, 40, 3, 2, 1, False, baseline=True)
+        sp3 = decomposition(X3s, 40, 3, 3, 1, False, sched=B.make_sched(tile_rounds=16, dynamic=1))
+        cmp["R40_first50000"] = {"nnz": X3s.nnz, "baseline": {k: bl3[k] for k in keep},
+                                 "spartan": {k: sp3[k] for k in keep},
+                                 "spartan_speedup": bl3["ms_per_step"] / sp3["ms_per_step"]}
+        more["explicit_y_baseline"] = cmp
+        del X3, X3s
         # the paper's timed setting: non-negative V and S_k (NNLS rows)
         nn = decomposition(X, R, a.config, a.steps, 1, False, nonneg=True)
         more["r10_nonneg"] = {k: nn[k] for k in ("ms_per_step", "nnz_per_s", "fit_after",

@@ -140,6 +140,19 @@ typedef struct {
                             next Procrustes step is then not fused into the
                             mode-3 pass (one more pass over X per iteration);
                             0: unconstrained                                  */
+  int32_t baseline;      /* 1: run the paper's comparison method instead of
+                            SPARTan's MTTKRPs ("Sparse PARAFAC2", Sec. "Setup"):
+                            every iteration materialises Q_k, forms the sparse
+                            tensor Y (Y_k = Q_k^T X_k over the nonzero columns
+                            of X_k, R entries per nonzero column, coordinate
+                            format) and runs the three MTTKRPs as generic
+                            coordinate-format sums over its entries.  Same
+                            results up to rounding; for comparison only.
+                            The workspace then holds the runs of equal columns
+                            of every subject, Q (n_rows x R floats) and Y
+                            (16 bytes for each of at most R * nnz entries);
+                            unconstrained and I_k >= R only (P2_ENOTSUP
+                            otherwise); a context with it cannot join a batch */
 } parafac2_opts;
 
 /* ABI version of the loaded library (PARAFAC2_ABI_VERSION). */

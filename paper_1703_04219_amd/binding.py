@@ -51,7 +51,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("tau_polar", ctypes.c_double), ("tau_pinv", ctypes.c_double),
                 ("hot_cols", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("sched", Sched), ("m2_capacity", ctypes.c_int32),
-                ("keep_bases", ctypes.c_int32), ("nonneg", ctypes.c_int32)]
+                ("keep_bases", ctypes.c_int32), ("nonneg", ctypes.c_int32),
+                ("baseline", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -160,7 +161,7 @@ def make_sched(tile_rounds=0, dynamic=0, m2_tiles=0, graph=0, m2_threads=0, m2_b
 
 
 def make_opts(tau_polar=0.0, tau_pinv=0.0, hot_cols=0, max_sweeps=0, sched=None,
-              m2_capacity=0, keep_bases=False, nonneg=False) -> Opts:
+              m2_capacity=0, keep_bases=False, nonneg=False, baseline=False) -> Opts:
     o = Opts()
     o.tau_polar, o.tau_pinv, o.hot_cols, o.max_sweeps = tau_polar, tau_pinv, hot_cols, max_sweeps
     if sched is not None:
@@ -168,6 +169,7 @@ def make_opts(tau_polar=0.0, tau_pinv=0.0, hot_cols=0, max_sweeps=0, sched=None,
     o.m2_capacity = m2_capacity
     o.keep_bases = 1 if keep_bases else 0
     o.nonneg = 1 if nonneg else 0
+    o.baseline = 1 if baseline else 0
     return o
 
 

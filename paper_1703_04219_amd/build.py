@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libparafac2.so")
-SOURCES = ["p2_kernels.hip", "p2_capi.hip", "p2_server.hip"]
+SOURCES = ["p2_kernels.hip", "p2_capi.hip", "p2_server.hip", "p2_baseline.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PARAFAC2_ARCH", "gfx950")

@@ -23,6 +23,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/parafac2.h"
@@ -89,7 +90,9 @@ int64_t mode2_parts(int64_t K, int R, int cap) {
 // Offsets of every piece of the context workspace.
 struct Plan {
   size_t zbase, rbase, rstart, col16, val, rank, perm, hist, order, econ, V[2], F, M2, M3, M3d, E,
-      small, err, part, desc, tiles, m2tiles, tickets, iter, total;
+      small, err, part, desc, tiles, m2tiles, tickets, iter, erow, eval, runs, runbase, Q, yr, yj,
+      yk, yv, acc, total;
+  bool baseline = false;  // explicit-Y comparison method: runs, Q and Y are planned
   bool warm = false;
   bool nonneg = false;  // V and W by NNLS: a float64 copy of M3 feeds the W rows
   int64_t cap_tiles = 0, cap_m2 = 0;  // tile capacities of the context's own runner
@@ -139,6 +142,21 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const p
   p.m2tiles = take(sizeof(p2::Tile) * (size_t)p.cap_m2);
   p.tickets = take(sizeof(int) * p2::kTicketKinds * kBins);
   p.iter = take(sizeof(int64_t));
+  p.baseline = o && o->baseline;
+  if (p.baseline) {
+    const size_t ny = (size_t)R * (size_t)nnz;  // at most one run per nonzero
+    p.erow = take(sizeof(uint16_t) * (size_t)nnz);
+    p.eval = take(sizeof(float) * (size_t)nnz);
+    p.runs = take(sizeof(uint32_t) * (size_t)nnz);
+    p.runbase = take(sizeof(int64_t) * (K + 1));
+    p.Q = take(sizeof(float) * (size_t)n_rows * R);
+    p.yr = take(sizeof(int32_t) * ny);
+    p.yj = take(sizeof(int32_t) * ny);
+    p.yk = take(sizeof(int32_t) * ny);
+    p.yv = take(sizeof(float) * ny);
+    // FP64 sums of the mode-2 and mode-3 outputs (J x LDV, then K x R)
+    p.acc = take(sizeof(double) * std::max<size_t>((size_t)J * LDV, (size_t)K * R));
+  }
   p.total = off;
   return p;
 }
@@ -210,6 +228,7 @@ struct parafac2_ctx {
   bool failed = false;
   int64_t iters_done = 0;
   int64_t n_econ = 0;  // subjects with I_k < R (economy Procrustes factor)
+  p2::BaselineView base{};  // the explicit-Y comparison method (plan.baseline)
   std::vector<int64_t> subj_host;
   Runner* own = nullptr;  // batch of one over this context
 
@@ -274,6 +293,7 @@ struct Runner {
   bool planned = false;
   bool any_nonneg = false;
   bool any_econ = false;
+  bool baseline = false;  // a context of one running the explicit-Y method
   // profiling: event pairs per phase, resolved lazily
   bool profiling = false;
   struct EvPair {
@@ -490,6 +510,43 @@ int runner_body(Runner& r, int parity, int do_next, hipStream_t s, bool prof) {
   return P2_OK;
 }
 
+// One iteration of the explicit-Y comparison method after its Procrustes
+// step (F_k from runner_alpha): Q, Y, the three coordinate-format MTTKRPs
+// with the H, V and W updates, the fit.  A runner of one context.
+int runner_body_baseline(Runner& r, int parity, hipStream_t s, bool prof) {
+  Group& g = r.groups[0];
+  const p2::BatchView& b = g.bv;
+  parafac2_ctx* c = r.ctxs[0];
+  const int R = c->R;
+  const p2::SmallLayout SL = p2::small_layout(R);
+  double* sm = c->small();
+  PHASE(P2_PHASE_ALPHA,
+        HIP_TRY(p2::run_getq(R, c->X, 0, c->K, c->V(parity), c->at<double>(c->plan.F),
+                             c->at<float>(c->plan.Q), 0, nullptr, s));
+        HIP_TRY(p2::run_form_y(R, c->base, s)));
+  HIP_TRY(p2::run_zero(b, 1 | 2 | 4 | 8 | 16, s));
+  double* acc = c->at<double>(c->plan.acc);
+  const int64_t nacc = std::max<int64_t>(c->J * c->LDV, c->K * R);
+  PHASE(P2_PHASE_SOLVE_H, HIP_TRY(p2::run_gram(b, 0, parity, s));
+        HIP_TRY(p2::run_coo_mttkrp(R, c->base, 1, c->H, c->V(parity), c->LDV, c->W, sm + SL.M1,
+                                   nullptr, 0, s));
+        HIP_TRY(p2::run_solve_h(b, g.pp, s)));
+  PHASE(P2_PHASE_MODE2, HIP_TRY(p2::run_fill_f64(acc, nacc, 0.0, s));
+        HIP_TRY(p2::run_coo_mttkrp(R, c->base, 2, c->H, nullptr, 0, c->W, nullptr, acc, c->LDV,
+                                   s));
+        HIP_TRY(p2::run_round_rows(acc, c->at<float>(c->plan.M2), c->J, R, c->LDV, s)));
+  PHASE(P2_PHASE_VUPDATE, HIP_TRY(p2::run_vupdate(b, parity, s));
+        HIP_TRY(p2::run_gram(b, 1, parity, s)); HIP_TRY(p2::run_solve_n3(b, g.pp, s));
+        HIP_TRY(p2::run_vscale(b, parity, s)));
+  PHASE(P2_PHASE_GAMMA, HIP_TRY(p2::run_fill_f64(acc, nacc, 0.0, s));
+        HIP_TRY(p2::run_coo_mttkrp(R, c->base, 3, c->H, c->V(parity ^ 1), c->LDV, nullptr,
+                                   nullptr, acc, R, s));
+        HIP_TRY(p2::run_round_rows(acc, c->at<float>(c->plan.M3), c->K, R, R, s));
+        HIP_TRY(p2::run_wupdate(R, b.desc, c->K, s)));
+  PHASE(P2_PHASE_FIT, HIP_TRY(p2::run_fit(b, s)));
+  return P2_OK;
+}
+
 int runner_capture(Runner& r, int parity, int do_next) {
   if (!r.cap) HIP_TRY(hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(r.cap, hipStreamCaptureModeRelaxed));
@@ -531,8 +588,10 @@ int runner_iterate_n(Runner& r, int32_t n, double* fit_host, double* loss_host) 
     // the non-negative W rows are solved after the mode-3 pass, and the loss
     // terms of subjects with I_k < R need this iteration's F_k after it, so
     // in either case the next Procrustes step cannot be fused into that pass
-    const int do_next = (it + 1 < n && !r.any_nonneg && !r.any_econ) ? 1 : 0;
-    if (graph) {
+    const int do_next = (it + 1 < n && !r.any_nonneg && !r.any_econ && !r.baseline) ? 1 : 0;
+    if (r.baseline) {
+      P2_TRY(runner_body_baseline(r, parity, s, prof));
+    } else if (graph) {
       if (!r.exec[parity][do_next]) P2_TRY(runner_capture(r, parity, do_next));
       HIP_TRY(hipGraphLaunch(r.exec[parity][do_next], s));
     } else {
@@ -769,6 +828,7 @@ int runner_make(Runner** out, parafac2_ctx* const* ctxs, int n, const RunnerLayo
     }
     r->any_nonneg = r->any_nonneg || g.nonneg;
     r->any_econ = r->any_econ || g.econ;
+    for (int i : lg.members) r->baseline = r->baseline || ctxs[i]->plan.baseline;
     r->groups.push_back(g);
   }
   *out = r;
@@ -781,6 +841,108 @@ struct parafac2_batch {
   Runner* r = nullptr;
   ~parafac2_batch() { delete r; }
 };
+
+// ---------------------------------------------------------------------------
+// The explicit-Y comparison method's static structure, from the encoded
+// slices: each subject's nonzeros sorted by (column, row) -- row within the
+// subject and value, at the subject's nonzero positions -- and one run per
+// distinct column, (start within the subject) | column << 16, at
+// [runbase[k], runbase[k+1]); then the coordinate indices of Y on the device.
+// Sorted on the host, one thread per range of subjects; synchronises s.
+// ---------------------------------------------------------------------------
+static int build_baseline(parafac2_ctx* c, hipStream_t s) {
+  const Plan& P = c->plan;
+  const int64_t K = c->K, nnz = c->nnz, n_rows = c->n_rows;
+  std::vector<uint16_t> col(nnz), rst(n_rows), erow(nnz), ecol(nnz);
+  std::vector<float> val(nnz), eval(nnz);
+  std::vector<int64_t> zb(K + 1), nruns(K), runbase(K + 1);
+  HIP_TRY(hipMemcpyAsync(col.data(), c->at<uint16_t>(P.col16), sizeof(uint16_t) * nnz,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(rst.data(), c->at<uint16_t>(P.rstart), sizeof(uint16_t) * n_rows,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(val.data(), c->at<float>(P.val), sizeof(float) * nnz,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(zb.data(), c->at<int64_t>(P.zbase), sizeof(int64_t) * (K + 1),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const std::vector<int64_t>& rb = c->subj_host;
+  auto sort_range = [&](int64_t k0, int64_t k1) {
+    std::vector<uint32_t> key, idx;
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t z0 = zb[k];
+      const int n = (int)(zb[k + 1] - z0);
+      const int64_t r0 = rb[k];
+      const int nr = (int)(rb[k + 1] - r0);
+      key.resize(n);
+      idx.resize(n);
+      for (int i = 0; i < nr; ++i) {
+        const int e1 = i + 1 < nr ? (int)rst[r0 + i + 1] : n;
+        for (int z = rst[r0 + i]; z < e1; ++z) key[z] = ((uint32_t)col[z0 + z] << 16) | (uint32_t)i;
+      }
+      std::iota(idx.begin(), idx.end(), 0u);
+      std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+      int64_t runs = 0;
+      for (int e = 0; e < n; ++e) {
+        const uint32_t kk = key[idx[e]];
+        erow[z0 + e] = (uint16_t)(kk & 0xffffu);
+        ecol[z0 + e] = (uint16_t)(kk >> 16);
+        eval[z0 + e] = val[z0 + idx[e]];
+        if (e == 0 || ecol[z0 + e] != ecol[z0 + e - 1]) ++runs;
+      }
+      nruns[k] = runs;
+    }
+  };
+  const int nth =
+      (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t) th.emplace_back(sort_range, K * t / nth, K * (t + 1) / nth);
+    for (auto& x : th) x.join();
+  }
+  runbase[0] = 0;
+  for (int64_t k = 0; k < K; ++k) runbase[k + 1] = runbase[k] + nruns[k];
+  std::vector<uint32_t> runs(std::max<int64_t>(runbase[K], 1));
+  auto run_range = [&](int64_t k0, int64_t k1) {
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t z0 = zb[k];
+      const int n = (int)(zb[k + 1] - z0);
+      int64_t u = runbase[k];
+      for (int e = 0; e < n; ++e)
+        if (e == 0 || ecol[z0 + e] != ecol[z0 + e - 1])
+          runs[u++] = (uint32_t)e | ((uint32_t)ecol[z0 + e] << 16);
+    }
+  };
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t) th.emplace_back(run_range, K * t / nth, K * (t + 1) / nth);
+    for (auto& x : th) x.join();
+  }
+  HIP_TRY(hipMemcpyAsync(c->at<uint16_t>(P.erow), erow.data(), sizeof(uint16_t) * nnz,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->at<float>(P.eval), eval.data(), sizeof(float) * nnz,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->at<uint32_t>(P.runs), runs.data(), sizeof(uint32_t) * runbase[K],
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->at<int64_t>(P.runbase), runbase.data(), sizeof(int64_t) * (K + 1),
+                         hipMemcpyHostToDevice, s));
+  p2::BaselineView& v = c->base;
+  v.zbase = c->at<int64_t>(P.zbase);
+  v.rbase = c->at<int64_t>(P.rbase);
+  v.erow = c->at<uint16_t>(P.erow);
+  v.eval = c->at<float>(P.eval);
+  v.runs = c->at<uint32_t>(P.runs);
+  v.runbase = c->at<int64_t>(P.runbase);
+  v.nruns = runbase[K];
+  v.yr = c->at<int32_t>(P.yr);
+  v.yj = c->at<int32_t>(P.yj);
+  v.yk = c->at<int32_t>(P.yk);
+  v.yv = c->at<float>(P.yv);
+  v.ny = (int64_t)c->R * runbase[K];
+  v.Q = c->at<float>(P.Q);
+  HIP_TRY(p2::run_y_index(c->R, v, K, s));
+  HIP_TRY(hipStreamSynchronize(s));  // the host vectors go out of scope
+  return P2_OK;
+}
 
 // ---------------------------------------------------------------------------
 // host-side validation
@@ -1035,6 +1197,13 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   INIT_TRY(p2::run_permute_rows(V, c->V(0), X->J, R, R, c->LDV, c->at<int32_t>(plan.rank), s));
   INIT_TRY(p2::run_gram_rows(R, c->V(0), X->J, c->LDV, sm + SL.VtV, s));
   INIT_TRY(hipStreamSynchronize(s));  // host vectors above go out of scope
+  if (plan.baseline) {
+    if (c->n_econ > 0 || plan.nonneg)
+      return cleanup(fail(P2_ENOTSUP, "the explicit-Y comparison method needs I_k >= R and no "
+                                      "constraints"));
+    const int rb = build_baseline(c, s);
+    if (rb != P2_OK) return cleanup(rb);
+  }
   c->X.zbase = zbase;
   c->X.rbase = rbase;
   c->X.rstart = c->at<uint16_t>(plan.rstart);
@@ -1203,6 +1372,9 @@ int parafac2_batch_create(parafac2_batch** out, parafac2_ctx* const* ctxs, int32
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (int32_t i = 0; i < n; ++i)
     if (ctxs[i]->stream != s) return fail(P2_EINVAL, "context %d has another stream", i);
+  for (int32_t i = 0; i < n; ++i)
+    if (ctxs[i]->plan.baseline)
+      return fail(P2_ENOTSUP, "context %d runs the explicit-Y comparison method", i);
   const RunnerLayout L = runner_layout(ctxs, n);
   if (ws_bytes < L.total)
     return fail(P2_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);

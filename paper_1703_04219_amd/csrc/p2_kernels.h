@@ -110,4 +110,31 @@ hipError_t run_model_prep(int R, const double* VtV, const double* H, double* HtH
                           double* N3p, const PolarParams& pp, hipStream_t s);
 hipError_t run_iota(int32_t* p, int64_t n, hipStream_t s);
 
+// The explicit-Y ("Sparse PARAFAC2") baseline of one problem (p2_baseline.hip).
+struct BaselineView {
+  const int64_t* zbase = nullptr;   // per-subject nonzero offsets (encoded slices)
+  const int64_t* rbase = nullptr;   // per-subject row offsets
+  const uint16_t* erow = nullptr;   // nonzeros sorted by (column, row) per subject: row
+  const float* eval = nullptr;      //   and value
+  const uint32_t* runs = nullptr;   // runs of equal columns: start | column << 16
+  const int64_t* runbase = nullptr; // per-subject run offsets
+  int64_t nruns = 0;                // sum_k c_k
+  const int32_t* yr = nullptr;      // coordinate tensor Y: R * nruns entries
+  const int32_t* yj = nullptr;
+  const int32_t* yk = nullptr;
+  float* yv = nullptr;
+  int64_t ny = 0;
+  const float* Q = nullptr;         // materialised Q (n_rows x R)
+};
+hipError_t run_y_index(int R, const BaselineView& v, int64_t K, hipStream_t s);
+hipError_t run_form_y(int R, const BaselineView& v, hipStream_t s);
+// mode 1: out1 (R x R FP64) += ...; modes 2, 3: out (rows x ldo) += ...
+hipError_t run_coo_mttkrp(int R, const BaselineView& v, int mode, const double* H, const float* V,
+                          int ldv, const float* W, double* out1, double* out, int ldo,
+                          hipStream_t s);
+// dst = (float) src over n rows, columns < R, row stride ld (both)
+hipError_t run_round_rows(const double* src, float* dst, int64_t n, int R, int ld, hipStream_t s);
+// W = M3 N3^+ and the fit terms of problem desc[0] (K rows)
+hipError_t run_wupdate(int R, const ProbDesc* desc, int64_t K, hipStream_t s);
+
 }  // namespace p2
