@@ -4,11 +4,12 @@ Every schedule and the batched launch compute the same iteration; results
 differ only in the order of floating-point atomic additions, and ALS carries
 such differences on, amplified on ill-conditioned subjects.  Tolerances:
   * after one iteration from the same state: factors within 1e-5 relative;
-  * over several iterations: fits within 1e-6, H and V within 1e-4 relative
-    (the batched-vs-single bar), W within 5e-4: the Procrustes step keeps the
-    directions of subjects with condition numbers up to ~3e6, and the W rows
-    of those few subjects change by about 1e-7 times the condition number
-    squared when the shared factors move by 1e-7;
+  * over several iterations: fits within 1e-6, H, V and W within 1e-4
+    relative (measured: at most 9e-7 after 3 iterations); the warm-started
+    eigen-solves are held to 5e-4 for W, because they stop at the Jacobi
+    threshold from another starting basis, and the Procrustes step keeps the
+    directions of subjects with condition numbers up to ~3e6, whose W rows
+    move by about the threshold times the condition number (1.3e-4 measured);
   * a batch member against the FP64 oracle: the single-problem bar (MTTKRPs
     and factors 1e-4 relative, fit 1e-5).
 """
@@ -87,8 +88,9 @@ def test_batch_equals_one_problem_at_a_time(sched):
     print("max fit diff", np.abs(fb - fs).max(), flush=True)
     assert np.abs(fb - fs).max() <= 1e-6
     for a, b in zip(single, batched):
-        for x, y, bar in zip(_state(b), _state(a), (1e-4, 1e-4, 5e-4)):
-            assert rel(x, y) <= bar
+        errs = [rel(x, y) for x, y in zip(_state(b), _state(a))]
+        print("batched vs alone H/V/W", errs, flush=True)
+        assert max(errs) <= 1e-4
 
 
 @pytest.mark.parametrize("sched", [
@@ -112,7 +114,8 @@ def test_schedules_agree(sched):
           flush=True)
     assert max(one) <= 1e-5
     assert np.abs(fa - fr).max() <= 1e-6
-    assert max(three[:2]) <= 1e-4 and three[2] <= 5e-4
+    assert max(three[:2]) <= 1e-4
+    assert three[2] <= (5e-4 if sched.get("warm_polar") else 1e-4)
 
 
 def test_graph_replays_match_plain_launches():
@@ -134,8 +137,9 @@ def test_graph_replays_match_plain_launches():
     fp, fg = np.concatenate(fp), np.concatenate(fg)
     print("graph vs plain fits", np.abs(fg - fp).max(), flush=True)
     assert np.abs(fg - fp).max() <= 1e-6
-    for x, y, bar in zip(_state(graph), _state(plain), (1e-4, 1e-4, 5e-4)):
-        assert rel(x, y) <= bar
+    errs = [rel(x, y) for x, y in zip(_state(graph), _state(plain))]
+    print("graph vs plain H/V/W", errs, flush=True)
+    assert max(errs) <= 1e-4
 
 
 def test_autotune_keeps_the_iteration():
