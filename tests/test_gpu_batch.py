@@ -5,7 +5,7 @@ differ only in the order of floating-point atomic additions, and ALS carries
 such differences on, amplified on ill-conditioned subjects.  Tolerances:
   * after one iteration from the same state: factors within 1e-5 relative;
   * over several iterations: fits within 1e-6, H, V and W within 1e-4
-    relative (measured: at most 9e-7 after 3 iterations); the warm-started
+    relative (measured: at most 1.1e-6 after 3 iterations); the warm-started
     eigen-solves are held to 5e-4 for W, because they stop at the Jacobi
     threshold from another starting basis, and the Procrustes step keeps the
     directions of subjects with condition numbers up to ~3e6, whose W rows
