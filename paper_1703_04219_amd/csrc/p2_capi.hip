@@ -89,7 +89,7 @@ int64_t mode2_parts(int64_t K, int R, int cap) {
 
 // Offsets of every piece of the context workspace.
 struct Plan {
-  size_t zbase, rbase, rstart, col16, val, rank, perm, hist, order, econ, V[2], F, M2, M3, M3d, E,
+  size_t zbase, rbase, rstart, nzrow, col16, val, rank, perm, hist, order, econ, V[2], F, M2, M3, M3d, E,
       small, err, part, desc, tiles, m2tiles, tickets, iter, erow, eval, runs, runbase, Q, yr, yj,
       yk, yv, acc, total;
   bool baseline = false;  // explicit-Y comparison method: runs, Q and Y are planned
@@ -117,6 +117,7 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const p
   p.zbase = take(sizeof(int64_t) * (K + 1));
   p.rbase = take(sizeof(int64_t) * (K + 1));
   p.rstart = take(sizeof(uint16_t) * (size_t)n_rows);
+  p.nzrow = take(sizeof(uint16_t) * (size_t)nnz);
   p.col16 = take(sizeof(uint16_t) * (size_t)nnz);
   p.val = take(sizeof(float) * (size_t)nnz);
   p.rank = take(sizeof(int32_t) * J);
@@ -1190,7 +1191,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   INIT_TRY(p2::run_fill_f64(reinterpret_cast<double*>(c->at<int64_t>(plan.iter)), 1, 0.0, s));
   INIT_TRY(p2::run_encode(X->subj_ptr, X->row_ptr, X->col, X->val, X->K, X->nnz,
                           c->at<int32_t>(plan.rank), c->at<uint16_t>(plan.rstart),
-                          c->at<uint16_t>(plan.col16), c->at<float>(plan.val), sm + SL.nx2, s));
+                          c->at<uint16_t>(plan.nzrow), c->at<uint16_t>(plan.col16), c->at<float>(plan.val), sm + SL.nx2, s));
   if (plan.warm) INIT_TRY(p2::run_eye_basis(c->at<float>(plan.E), X->K, R, s));
   INIT_TRY(p2::run_fill_f32(c->V(0), X->J * c->LDV, 0.f, s));
   INIT_TRY(p2::run_fill_f32(c->V(1), X->J * c->LDV, 0.f, s));
@@ -1207,6 +1208,7 @@ int parafac2_init(parafac2_ctx** out, const parafac2_csr* X, int32_t R, double* 
   c->X.zbase = zbase;
   c->X.rbase = rbase;
   c->X.rstart = c->at<uint16_t>(plan.rstart);
+  c->X.nzrow = c->at<uint16_t>(plan.nzrow);
   c->X.col = c->at<uint16_t>(plan.col16);
   c->X.val = c->at<float>(plan.val);
   c->cur = 0;

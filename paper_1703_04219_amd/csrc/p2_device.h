@@ -84,6 +84,7 @@ struct XEnc {
   const uint16_t* rstart;
   const uint16_t* col;
   const float* val;
+  const uint16_t* nzrow;  // row of each nonzero, relative to its subject
   __device__ __forceinline__ Subj subj(int64_t k) const {
     Subj s;
     s.z0 = glob(zbase)[k];

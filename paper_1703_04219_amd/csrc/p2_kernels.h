@@ -96,8 +96,8 @@ hipError_t run_validate(const int64_t* subj_ptr, const int64_t* row_ptr, const i
                         int min_rows, int* err, int64_t* zbase, int64_t* rbase, hipStream_t s);
 hipError_t run_encode(const int64_t* subj_ptr, const int64_t* row_ptr, const int32_t* col,
                       const float* val, int64_t K, int64_t nnz, const int32_t* rank,
-                      uint16_t* rstart, uint16_t* col16, float* val_out, double* nx2,
-                      hipStream_t s);
+                      uint16_t* rstart, uint16_t* nzrow, uint16_t* col16, float* val_out,
+                      double* nx2, hipStream_t s);
 hipError_t run_col_hist(const int32_t* col, int64_t nnz, int64_t J, unsigned int* hist,
                         hipStream_t s);
 hipError_t run_permute_rows(const float* src, float* dst, int64_t J, int R, int ld_src,

@@ -18,6 +18,8 @@
 #include "p2_device.h"
 #include "p2_kernels.h"
 
+#include <utility>
+
 namespace p2 {
 
 // ---------------------------------------------------------------------------
@@ -399,12 +401,19 @@ __global__ void __launch_bounds__(256, PolarLds<R>::kMinWaves) k_gamma(const Pro
 // ---------------------------------------------------------------------------
 // k_mode2: M2 += X_k^T (A_k E_k),  E_k = F_k^T H diag(w_k)  (equation
 // (mttkrp2_3): for every nonzero column j of X_k, row j of Y_k^T H diag(w_k)).
-// One lane per row: it gathers A(i, :) into registers, forms D(i, :) =
-// A(i, :) E_k with E_k staged in the group's LDS, and adds x_ij D(i, :) into
-// M2(j, :) -- in the block's LDS copy for the hot columns (ids < hot, the most
-// frequent after relabelling), with global atomics for the rest.  Each tile
-// writes its hot partial sums, without atomics, to its own slot among its
-// problem's partial sums; k_mode2_reduce adds them up per problem.
+// This kernel serves R > 16 (k_mode2_dpp below serves R <= 16).  One lane per
+// row: it gathers A(i, :) into registers, forms D(i, :) = A(i, :) E_k with
+// E_k staged in the group's LDS, and adds x_ij D(i, :) into M2(j, :):
+//  * hot columns (ids < hot, the most frequent after relabelling) into the
+//    block's FP64 partial sums in LDS; each tile writes them, without
+//    atomics, to its own slot among its problem's partial sums, and
+//    k_mode2_reduce adds the slots up per problem;
+//  * cold columns through a per-wave LDS queue, added to M2 when the queue is
+//    full and at the end of a tile, with the lanes of one atomic instruction
+//    on consecutive (row, component) entries.  Device-wide float atomics are
+//    carried out past the L2, one memory transaction per 32-byte sector an
+//    instruction touches, and they retire in order with the wave's loads, so
+//    an atomic issued per row would also hold up the next wait for a load.
 // ---------------------------------------------------------------------------
 constexpr int kMode2Threads = 1024;
 
@@ -412,7 +421,19 @@ constexpr int kMode2Threads = 1024;
 #define P2_M2_T10 2
 #endif
 #ifndef P2_M2_NT10
-#define P2_M2_NT10 3
+#define P2_M2_NT10 0
+#endif
+#ifndef P2_M2_NT20
+#define P2_M2_NT20 0
+#endif
+#ifndef P2_M2D_QUEUE
+#define P2_M2D_QUEUE 16
+#endif
+#ifndef P2_M2D_CHUNK
+#define P2_M2D_CHUNK 4
+#endif
+#ifndef P2_M2_QUEUE
+#define P2_M2_QUEUE 16
 #endif
 template <int R>
 struct Mode2Lds {
@@ -428,11 +449,36 @@ struct Mode2Lds {
   static constexpr int kRowsPerStep = R <= 6 ? 4 : (R <= 10 ? P2_M2_T10 : (R <= 20 ? 2 : 1));
   // most frequent columns whose partial sums each lane keeps in registers
   // (as many as the register budget of the rank's block size allows)
-  static constexpr int kTopReg = R <= 10 ? P2_M2_NT10 : (R == 20 ? 3 : (R == 32 ? 1 : 0));
-  // floats before the group buffers: the hot partial sums, rounded up so
-  // that E rows are 16-byte aligned
-  static constexpr int hot_floats(int hot) { return (hot * R + 3) & ~3; }
+  static constexpr int kTopReg = R <= 10 ? P2_M2_NT10 : (R == 20 ? P2_M2_NT20 : 0);
+  // floats before the group buffers: the hot partial sums, in FP64 (LDS
+  // float atomics are carried out one lane at a time, about 3 cycles per
+  // lane, while FP64 ones take about 24 cycles per wave instruction), rounded
+  // up so that E rows are 16-byte aligned
+  static constexpr int hot_floats(int hot) { return (2 * hot * R + 3) & ~3; }
+  // per wave after all group buffers: a count, then up to kQueue staged cold
+  // updates (column ids, then R-float rows), added to M2 when the queue is
+  // full and at the end of a tile
+  static constexpr int kQueue = P2_M2_QUEUE;
+  static constexpr int kQueueFloats = (4 + kQueue * (R + 1) + 3) & ~3;
 };
+
+// Adds the n staged rows of a wave's cold queue to M2 with the active lanes
+// on consecutive (row, component) entries, so that the lanes of one atomic
+// instruction touch a few rows of M2 (one memory transaction per 32-byte
+// sector) rather than one row each.
+template <int R>
+__device__ __forceinline__ void cold_flush(float* M2, const int* qj, const float* qv, int n) {
+  constexpr int LDV = Geo<R>::LDV;
+  const uint64_t am = __ballot(true);
+  const int nact = __popcll(am);
+  const int me = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(am >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)am, 0u));
+  for (int v = me; v < n * R; v += nact) {
+    const int e = v / R;
+    gadd(M2 + (size_t)qj[e] * LDV + (v - e * R), qv[v]);
+  }
+  wave_sync();
+}
 
 template <int R>
 __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDesc* __restrict__ P,
@@ -448,9 +494,17 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
   const int wave = threadIdx.x / kWave;
   const int gpb = (blockDim.x / kWave) * GPW;
   const int gslot = wave * GPW + (L.live ? L.grp : 0);
-  float* shM2 = reinterpret_cast<float*>(p2_smem);  // up to max_hot x R
-  double* Es = reinterpret_cast<double*>(shM2 + Mode2Lds<R>::hot_floats(max_hot) +
+  double* shM2 = reinterpret_cast<double*>(p2_smem);  // up to max_hot x R
+  float* shM2f = reinterpret_cast<float*>(p2_smem);
+  double* Es = reinterpret_cast<double*>(shM2f + Mode2Lds<R>::hot_floats(max_hot) +
                                          gslot * Mode2Lds<R>::kPerGroup);
+  constexpr int QN = Mode2Lds<R>::kQueue;
+  int* qcount = reinterpret_cast<int*>(shM2f + Mode2Lds<R>::hot_floats(max_hot) +
+                                       gpb * Mode2Lds<R>::kPerGroup +
+                                       wave * Mode2Lds<R>::kQueueFloats);
+  int* qj = qcount + 4;
+  float* qv = reinterpret_cast<float*>(qj + QN);
+  if (L.lane == 0) qcount[0] = 0;
   const int c = L.j;
   const bool real = c < R;
   const int cc = real ? c : 0;
@@ -467,7 +521,7 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
     float* __restrict__ M2 = D.M2;
     const int hot = min(D.hot, max_hot);
     __syncthreads();
-    for (int q = threadIdx.x; q < hot * R; q += blockDim.x) shM2[q] = 0.f;
+    for (int q = threadIdx.x; q < hot * R; q += blockDim.x) shM2[q] = 0.0;
     __syncthreads();
     // the kTopReg most frequent columns (ids 0.. after the relabelling) are
     // summed in registers per lane and added to the LDS partial sums once per
@@ -584,42 +638,75 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
           }
 #pragma unroll
           for (int t = 0; t < T; ++t) {
-            if (zs[t] >= ze[t]) continue;
+            const int nz = ze[t] - zs[t];  // 0 for rows past the subject
             // D(i, :) = A(i, :) E in FP64, reading E rows as 16-byte LDS vectors
             // (NC columns: the padding of E beyond them is never read)
             double d[NC];
 #pragma unroll
             for (int q = 0; q < NC; ++q) d[q] = 0.0;
+            if (nz > 0) {
 #pragma unroll
-            for (int p = 0; p < R; ++p) {
-              const double ap = (double)a[t][p];
-              const double2* e2 = reinterpret_cast<const double2*>(Es + p * NC);
+              for (int p = 0; p < R; ++p) {
+                const double ap = (double)a[t][p];
+                const double2* e2 = reinterpret_cast<const double2*>(Es + p * NC);
 #pragma unroll
-              for (int q = 0; q < NC / 2; ++q) {
-                const double2 e = e2[q];
-                d[2 * q + 0] = fma(ap, e.x, d[2 * q + 0]);
-                d[2 * q + 1] = fma(ap, e.y, d[2 * q + 1]);
+                for (int q = 0; q < NC / 2; ++q) {
+                  const double2 e = e2[q];
+                  d[2 * q + 0] = fma(ap, e.x, d[2 * q + 0]);
+                  d[2 * q + 1] = fma(ap, e.y, d[2 * q + 1]);
+                }
               }
             }
-            for (int z = zs[t]; z < ze[t]; ++z) {
-              const int j = (z == zs[t]) ? j0[t] : (int)cl[z];
-              const float x = (z == zs[t]) ? x0[t] : vl[z];
+            // one nonzero of the row per lane and round; the rounds run while
+            // any active lane of the wave has one left
+            for (int r = 0; __ballot(r < nz) != 0ull; ++r) {
+              const bool act = r < nz;
+              int j = 0;
+              float x = 0.f;
+              if (act) {
+                j = (r == 0) ? j0[t] : (int)cl[zs[t] + r];
+                x = (r == 0) ? x0[t] : vl[zs[t] + r];
+              }
 #pragma unroll
               for (int u = 0; u < NT; ++u) {
                 const float xt = (j == u) ? x : 0.f;
 #pragma unroll
                 for (int q = 0; q < R; ++q) top[u][q] = fmaf(xt, (float)d[q], top[u][q]);
               }
-              if (j < NT && j < hot) {
-                // summed in top[j] above, flushed once per tile below
-              } else if (j < hot) {
-                float* dst = shM2 + j * R;
+              // hot columns below NT are summed in top[] above and flushed
+              // once per tile below
+              if (act && j >= NT && j < hot) {
+                double* dst = shM2 + j * R;
 #pragma unroll
-                for (int q = 0; q < R; ++q) atomicAdd(dst + q, x * (float)d[q]);
-              } else {
-                float* dst = M2 + (size_t)j * LDV;
+                for (int q = 0; q < R; ++q) atomicAdd(dst + q, (double)x * d[q]);
+              }
+              // cold columns: staged in the wave's queue (count in LDS, so
+              // that every group of the wave sees it on whichever path it is)
+              const bool cold = act && j >= hot;
+              const uint64_t cm = __ballot(cold);
+              if (cm != 0ull) {
+                const int ncold = __popcll(cm);
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+                int base = qcount[0];
+                if (base + ncold > QN) {
+                  cold_flush<R>(M2, qj, qv, base);
+                  base = 0;
+                }
+                const int slot = base + rank;
+                if (cold) {
+                  if (slot < QN) {
+                    qj[slot] = j;
 #pragma unroll
-                for (int q = 0; q < R; ++q) gadd(dst + q, x * (float)d[q]);
+                    for (int q = 0; q < R; ++q) qv[slot * R + q] = x * (float)d[q];
+                  } else {
+                    float* dst = M2 + (size_t)j * LDV;
+#pragma unroll
+                    for (int q = 0; q < R; ++q) gadd(dst + q, x * (float)d[q]);
+                  }
+                }
+                if (cold && rank == 0) qcount[0] = min(QN, base + ncold);
+                wave_sync();
               }
             }
           }
@@ -627,17 +714,294 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
         wave_sync();
       }
     }
+    cold_flush<R>(M2, qj, qv, qcount[0]);
+    if (L.lane == 0) qcount[0] = 0;
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
       if (u < hot) {
 #pragma unroll
         for (int q = 0; q < R; ++q)
-          if (top[u][q] != 0.f) atomicAdd(shM2 + u * R + q, top[u][q]);
+          if (top[u][q] != 0.f) atomicAdd(shM2 + u * R + q, (double)top[u][q]);
       }
     }
     __syncthreads();
     P2_GLOBAL float* mine = glob(D.part) + (int64_t)tile.slot * hot * R;
-    for (int q = threadIdx.x; q < hot * R; q += blockDim.x) mine[q] = shM2[q];
+    for (int q = threadIdx.x; q < hot * R; q += blockDim.x) mine[q] = (float)shM2[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_mode2 for R <= 16.  A subject's group is one 16-lane DPP row.
+//  * E_k in registers: lane p (p < R) forms row p of E_k = F_k^T H diag(w_k)
+//    from its contiguous column of F_k, and every lane forms D(i, :) =
+//    A(i, :) E_k with one v_fmac_f64 per product whose first source is read
+//    from lane p of the row (row_newbcast:p); no LDS traffic per row.
+//  * One nonzero per lane and step: lane c takes nonzero zb + c of the
+//    subject, gathers the whole row of that nonzero and adds x_ij D(i, :) for
+//    its own nonzero, so a step makes each update once (a lane per row would
+//    need as many rounds as the longest row of the wave has nonzeros).
+//  * Hot columns add into FP64 partial sums in LDS: LDS float atomics are
+//    carried out one lane at a time (about 3 cycles per lane), FP64 ones take
+//    about 24 cycles per wave instruction.
+//  * Cold columns are staged in a per-wave LDS queue and added to M2 only when
+//    the queue is full and at the end of a tile, with the lanes on
+//    consecutive entries.  A device-wide atomic is acknowledged from memory,
+//    and a wave's vector memory counter retires in order, so an atomic issued
+//    in a step would hold up the wait for every later load of the wave.
+// ---------------------------------------------------------------------------
+template <int R>
+struct Mode2Dpp {
+  static constexpr int kLanes = 16;               // one DPP row per subject
+  static constexpr int kGroups = kWave / kLanes;  // subjects per wave
+  // steps whose nonzero indices a lane loads at once (one nonzero per step)
+  static constexpr int kChunk = P2_M2D_CHUNK;
+  static constexpr int kTopReg = R <= 10 ? P2_M2_NT10 : 0;
+  // H' as floats after the hot partial sums
+  static constexpr int kHFloats = (R * R + 3) & ~3;
+  // per wave after H': a count, then up to kQueue staged cold updates (column
+  // ids, then R-float rows); they are added to M2 only when the queue is full
+  // and at the end of a tile
+  static constexpr int kQueue = P2_M2D_QUEUE;
+  static constexpr int kQueueFloats = (4 + kQueue * (R + 1) + 3) & ~3;
+};
+template <int R> constexpr bool kMode2UsesDpp = R <= 16;
+
+// d += a * E(P, q), E(P, q) held by lane P of this lane's 16-lane row in e.
+// A DPP read needs five wait states after EXEC was written and two after its
+// source VGPR was written by the VALU; the caller issues s_nop 4 (dpp_guard)
+// before the first product of each row and after forming e.
+template <int P>
+__device__ __forceinline__ void fmac_bcast(double& d, double e, double a) {
+  asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+               : "+v"(d)
+               : "v"(e), "v"(a), "n"(P));
+}
+__device__ __forceinline__ void dpp_guard() { asm volatile("s_nop 4" ::: "memory"); }
+
+// d(q) += sum_p a(p) E(p, q), a widened per p
+template <int R, int P, int N>
+__device__ __forceinline__ void dpp_row_products(double (&d)[R], const double (&e)[R],
+                                                 const float (&a)[N]) {
+  const double ap = (double)a[P];
+#pragma unroll
+  for (int q = 0; q < R; ++q) fmac_bcast<P>(d[q], e[q], ap);
+}
+template <int R, int N, int... P>
+__device__ __forceinline__ void dpp_products(double (&d)[R], const double (&e)[R],
+                                             const float (&a)[N],
+                                             std::integer_sequence<int, P...>) {
+  (dpp_row_products<R, P, N>(d, e, a), ...);
+}
+
+template <int R>
+__global__ void __launch_bounds__(kMode2Threads) k_mode2_dpp(const ProbDesc* __restrict__ P,
+                                                            const Tile* __restrict__ T,
+                                                            int ntiles, int* tickets, int parity,
+                                                            int max_hot) {
+  using MD = Mode2Dpp<R>;
+  constexpr int G = MD::kLanes;
+  constexpr int LDV = Geo<R>::LDV;
+  __shared__ int sh_t[2];
+  if (threadIdx.x == 0) sh_t[1] = 0;
+  const int c = threadIdx.x & (G - 1);  // lane in the group (and DPP row)
+  const int wave = threadIdx.x / kWave;
+  const int gpb = (blockDim.x / kWave) * MD::kGroups;
+  const int gslot = wave * MD::kGroups + (threadIdx.x & (kWave - 1)) / G;
+  double* shM2 = reinterpret_cast<double*>(p2_smem);  // up to max_hot x R
+  float* shH = reinterpret_cast<float*>(p2_smem) + Mode2Lds<R>::hot_floats(max_hot);
+  constexpr int QN = MD::kQueue;
+  int* qcount = reinterpret_cast<int*>(shH + MD::kHFloats + wave * MD::kQueueFloats);
+  int* qj = qcount + 4;
+  float* qv = reinterpret_cast<float*>(qj + QN);
+  if ((threadIdx.x & (kWave - 1)) == 0) qcount[0] = 0;
+  const int pc = c < R ? c : 0;  // the row of E_k this lane forms
+  for (int i = 0;; ++i) {
+    const int t = claim_tile(ntiles, tickets, i, sh_t);
+    if (t < 0) break;
+    const Tile tile = T[t];
+    if (tile.k0 >= tile.k1) continue;
+    const ProbDesc& D = P[tile.p];
+    const XEnc X = D.X;
+    const float* __restrict__ V = D.V[parity];
+    const float* __restrict__ W = D.W;
+    const double* __restrict__ F = D.F;
+    float* __restrict__ M2 = D.M2;
+    const int hot = min(D.hot, max_hot);
+    __syncthreads();
+    for (int q = threadIdx.x; q < hot * R; q += blockDim.x) shM2[q] = 0.0;
+    // H' in FP32 (as in k_mode2: Q_k = A F^T has orthonormal columns, so a
+    // rounding of H' moves D by Q_k dH diag(w'), unscaled by the subject's
+    // condition number)
+    for (int q = threadIdx.x; q < R * R; q += blockDim.x) shH[q] = (float)glob(D.H)[q];
+    __syncthreads();
+    constexpr int NT = MD::kTopReg;
+    float top[NT > 0 ? NT : 1][R];
+#pragma unroll
+    for (int u = 0; u < (NT > 0 ? NT : 1); ++u) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) top[u][q] = 0.f;
+    }
+    for (int64_t pos = tile.k0 + gslot; pos < tile.k1; pos += gpb) {
+      const int64_t k = subject_at(D, pos);
+      const Subj s = X.subj(k);
+      // E(p, q) = w(q) sum_r F(r, p) H(r, q) for p = pc: F(:, p) is contiguous
+      // (F(r, p) at p * R + r), so the group loads F_k coalesced
+      double e[R];
+      {
+        // every load of the subject is issued before the first is used (the
+        // scheduler would otherwise interleave them with the products and
+        // wait for each in turn)
+        const P2_GLOBAL double* Fp = glob(F) + (size_t)k * R * R + pc * R;
+        double f[R];
+        float wq[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) f[r] = Fp[r];
+#pragma unroll
+        for (int q = 0; q < R; ++q) wq[q] = glob(W)[k * R + q];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          double acc = 0.0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc = fma(f[r], (double)shH[r * R + q], acc);
+          e[q] = acc * (double)wq[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) settle(e[q]);
+      dpp_guard();
+      // one nonzero per lane and step: lane c takes nonzero zb + c, gathers
+      // the whole row of that nonzero (its own term first) and adds x_ij D(i, :)
+      // for its nonzero only, so a step issues the R atomics of each of its 16
+      // nonzeros once (a lane per row needs as many rounds as the longest row
+      // of the wave has nonzeros)
+      const P2_GLOBAL uint16_t* __restrict__ rst = glob(X.rstart) + s.r0;
+      const P2_GLOBAL uint16_t* __restrict__ nzr = glob(X.nzrow) + s.z0;
+      const P2_GLOBAL uint16_t* __restrict__ cl = glob(X.col) + s.z0;
+      const P2_GLOBAL float* __restrict__ vl = glob(X.val) + s.z0;
+      // nonzeros in chunks of kChunk per lane: the rows, columns and values of
+      // a chunk are requested together (coalesced over the group) before the
+      // chunk's first step, so a step waits only for its V rows and row bounds
+      constexpr int NB = MD::kChunk;
+#pragma nounroll
+      for (int zc = 0; zc < s.nnz; zc += G * NB) {
+        uint32_t rjc[NB];  // row << 16 | column
+        float xc[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int zb = zc + c + b * G;
+          const int zz = zb < s.nnz ? zb : 0;
+          rjc[b] = ((uint32_t)nzr[zz] << 16) | (uint32_t)cl[zz];
+          xc[b] = vl[zz];
+        }
+        // the chunk's steps in one loop body: each step takes entry 0 and
+        // shifts the rest down (register arrays are not indexed at run time)
+#pragma nounroll
+        for (int b = 0; b < NB; ++b) {
+        const int zb = zc + b * G;
+        if (zb >= s.nnz) break;  // uniform over the group
+        const int z = zb + c;
+        const bool ok = z < s.nnz;
+        const int ir = (int)(rjc[0] >> 16);
+        const int j = (int)(rjc[0] & 0xffffu);
+        const float x = ok ? xc[0] : 0.f;
+#pragma unroll
+        for (int u = 0; u + 1 < NB; ++u) {
+          rjc[u] = rjc[u + 1];
+          xc[u] = xc[u + 1];
+        }
+        // V(j, :) and the row's bounds, in flight together
+        p2_f4 v4[LDV / 4];
+        const float* vr = V + (size_t)j * LDV;
+#pragma unroll
+        for (int q = 0; q < LDV / 4; ++q) v4[q] = ldg4(vr + 4 * q);
+        const int rs0 = rst[ir];
+        const int re0 = rst[ir + 1 < s.nrows ? ir + 1 : ir];
+        float a[LDV];
+#pragma unroll
+        for (int q = 0; q < LDV / 4; ++q) {
+          a[4 * q + 0] = x * v4[q].x;
+          a[4 * q + 1] = x * v4[q].y;
+          a[4 * q + 2] = x * v4[q].z;
+          a[4 * q + 3] = x * v4[q].w;
+        }
+        const int rs = ok ? rs0 : 0;
+        const int re = ok ? ((ir + 1 < s.nrows) ? re0 : s.nnz) : 0;
+        for (int y = rs; y < re; ++y) {
+          if (y == z) continue;
+          const float xo = vl[y];
+          const float* vr = V + (size_t)cl[y] * LDV;
+#pragma unroll
+          for (int q = 0; q < LDV / 4; ++q) {
+            const p2_f4 v4 = ldg4(vr + 4 * q);
+            a[4 * q + 0] = fmaf(xo, v4.x, a[4 * q + 0]);
+            a[4 * q + 1] = fmaf(xo, v4.y, a[4 * q + 1]);
+            a[4 * q + 2] = fmaf(xo, v4.z, a[4 * q + 2]);
+            a[4 * q + 3] = fmaf(xo, v4.w, a[4 * q + 3]);
+          }
+        }
+        // D(i, :) = A(i, :) E_k for every lane of the group (lanes past the
+        // subject have A = 0)
+        double d[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) d[q] = 0.0;
+        dpp_guard();
+        dpp_products<R>(d, e, a, std::make_integer_sequence<int, R>{});
+#pragma unroll
+        for (int w = 0; w < NT; ++w) {
+          const float xt = (j == w) ? x : 0.f;
+#pragma unroll
+          for (int q = 0; q < R; ++q) top[w][q] = fmaf(xt, (float)d[q], top[w][q]);
+        }
+        if (ok && j >= NT && j < hot) {
+          double* dst = shM2 + j * R;
+#pragma unroll
+          for (int q = 0; q < R; ++q) atomicAdd(dst + q, (double)x * d[q]);
+        }
+        // cold columns: staged in the wave's queue (the count is kept in LDS,
+        // where every group of the wave sees it whichever path it is on)
+        const bool cold = ok && j >= hot;
+        const uint64_t cm = __ballot(cold);
+        if (cm != 0ull) {
+          const int ncold = __popcll(cm);
+          const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+          int base = qcount[0];
+          if (base + ncold > QN) {
+            cold_flush<R>(M2, qj, qv, base);
+            base = 0;
+          }
+          const int slot = base + rank;
+          if (cold) {
+            if (slot < QN) {
+              qj[slot] = j;
+#pragma unroll
+              for (int q = 0; q < R; ++q) qv[slot * R + q] = x * (float)d[q];
+            } else {
+              float* dst = M2 + (size_t)j * LDV;
+#pragma unroll
+              for (int q = 0; q < R; ++q) gadd(dst + q, x * (float)d[q]);
+            }
+          }
+          if (cold && rank == 0) qcount[0] = min(QN, base + ncold);
+          wave_sync();
+        }
+        }
+      }
+    }
+    cold_flush<R>(M2, qj, qv, qcount[0]);
+    if ((threadIdx.x & (kWave - 1)) == 0) qcount[0] = 0;
+#pragma unroll
+    for (int w = 0; w < NT; ++w) {
+      if (w < hot) {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+          if (top[w][q] != 0.f) atomicAdd(shM2 + w * R + q, (double)top[w][q]);
+      }
+    }
+    __syncthreads();
+    P2_GLOBAL float* mine = glob(D.part) + (int64_t)tile.slot * hot * R;
+    for (int q = threadIdx.x; q < hot * R; q += blockDim.x) mine[q] = (float)shM2[q];
   }
 }
 
@@ -1631,12 +1995,15 @@ __global__ void k_validate_subj(const int64_t* __restrict__ subj_ptr,
 
 __global__ void k_encode_rows(const int64_t* __restrict__ subj_ptr,
                               const int64_t* __restrict__ row_ptr, int64_t K,
-                              uint16_t* __restrict__ rstart) {
+                              uint16_t* __restrict__ rstart, uint16_t* __restrict__ nzrow) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r0 = subj_ptr[k], r1 = subj_ptr[k + 1];
     const int64_t z0 = row_ptr[r0];
-    for (int64_t i = r0; i < r1; ++i) rstart[i] = (uint16_t)(row_ptr[i] - z0);
+    for (int64_t i = r0; i < r1; ++i) {
+      rstart[i] = (uint16_t)(row_ptr[i] - z0);
+      for (int64_t z = row_ptr[i]; z < row_ptr[i + 1]; ++z) nzrow[z] = (uint16_t)(i - r0);
+    }
   }
 }
 
@@ -1794,16 +2161,33 @@ template <int R> constexpr int proj_threads() {
 template <int R> constexpr int getq_threads() {
   return pick_threads<R>(0, getq_group<R>(), kLdsBudget, 256);
 }
-// mode 2: the per-group buffers may take at most half of the LDS, the hot
-// column partial sums take the rest
+// mode 2: the per-group buffers may take at most half of the LDS, the waves'
+// cold-update queues and the hot column partial sums take the rest; the DPP
+// kernel (R <= 16) has no per-group buffers, only H' next to the hot sums
 template <int R> constexpr int mode2_threads() {
+  if constexpr (kMode2UsesDpp<R>) return kMode2Threads;
   return pick_threads<R>(0, mode2_group<R>(), kLdsBudget / 2, Mode2Lds<R>::kMaxThreads);
 }
+template <int R> constexpr size_t mode2_groups_bytes_at(int threads) {
+  if constexpr (kMode2UsesDpp<R>)
+    return sizeof(float) * (Mode2Dpp<R>::kHFloats + (size_t)(threads / kWave) * Mode2Dpp<R>::kQueueFloats);
+  return (size_t)(threads / kWave) *
+         (Geo<R>::GPW * mode2_group<R>() + sizeof(float) * Mode2Lds<R>::kQueueFloats);
+}
+template <int R> constexpr size_t mode2_ebytes_at(int threads) {
+  if constexpr (kMode2UsesDpp<R>) return 0;
+  return (size_t)(threads / kWave) * Geo<R>::GPW * mode2_group<R>();
+}
+// subject groups per wave of the rank's mode-2 kernel
+template <int R> constexpr int mode2_gpw() {
+  if constexpr (kMode2UsesDpp<R>) return Mode2Dpp<R>::kGroups;
+  return Geo<R>::GPW;
+}
 template <int R> constexpr size_t mode2_groups_bytes() {
-  return (size_t)(mode2_threads<R>() / kWave) * Geo<R>::GPW * mode2_group<R>();
+  return mode2_groups_bytes_at<R>(mode2_threads<R>());
 }
 template <int R> constexpr int max_hot_t() {
-  return (int)((kLdsBudget - 2048 - mode2_groups_bytes<R>()) / (sizeof(float) * R));
+  return (int)((kLdsBudget - 2048 - mode2_groups_bytes<R>()) / (sizeof(double) * R));
 }
 
 #define P2_RANKS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(32) X(40)
@@ -1839,7 +2223,7 @@ P2_RANKS(P2_CHECK_PLAN)
   }
 
 template <int R> constexpr int polar_gpb() { return (gamma_threads<R>() / kWave) * Geo<R>::GPW; }
-template <int R> constexpr int mode2_gpb() { return (mode2_threads<R>() / kWave) * Geo<R>::GPW; }
+template <int R> constexpr int mode2_gpb() { return (mode2_threads<R>() / kWave) * mode2_gpw<R>(); }
 template <int R> constexpr size_t alpha_lds() {
   return alpha_shared<R>() + (size_t)(alpha_threads<R>() / kWave) * Geo<R>::GPW * alpha_group<R>();
 }
@@ -1848,9 +2232,6 @@ template <int R> constexpr size_t gamma_lds() {
 }
 template <int R> size_t mode2_lds(int hot) {
   return sizeof(float) * (size_t)Mode2Lds<R>::hot_floats(hot) + mode2_groups_bytes<R>();
-}
-template <int R> size_t mode2_groups_bytes_at(int threads) {
-  return (size_t)(threads / kWave) * Geo<R>::GPW * mode2_group<R>();
 }
 
 int device_cus() {
@@ -1917,16 +2298,19 @@ hipError_t plan_t(BatchView& b) {
   int threads = b.m2_threads > 0 ? b.m2_threads : mode2_threads<R>();
   threads = threads / kWave * kWave;
   if (threads > Mode2Lds<R>::kMaxThreads) threads = Mode2Lds<R>::kMaxThreads;
-  while (threads > kWave && mode2_groups_bytes_at<R>(threads) > budget / 2) threads -= kWave;
+  while (threads > kWave && mode2_ebytes_at<R>(threads) > budget / 2) threads -= kWave;
   if (threads < kWave || mode2_groups_bytes_at<R>(threads) + 2048 > budget)
     return hipErrorInvalidConfiguration;
-  int hot = (int)((budget - 2048 - mode2_groups_bytes_at<R>(threads)) / (sizeof(float) * R));
+  int hot = (int)((budget - 2048 - mode2_groups_bytes_at<R>(threads)) / (sizeof(double) * R));
   if (hot > b.max_hot) hot = b.max_hot;
   b.m2_threads = threads;
   b.m2_hot = hot;
   b.m2_lds = sizeof(float) * (size_t)Mode2Lds<R>::hot_floats(hot) +
              mode2_groups_bytes_at<R>(threads);
-  return resident_grid(k_mode2<R>, threads, b.m2_lds, b.nm2, &b.grid_mode2);
+  if constexpr (kMode2UsesDpp<R>)
+    return resident_grid(k_mode2_dpp<R>, threads, b.m2_lds, b.nm2, &b.grid_mode2);
+  else
+    return resident_grid(k_mode2<R>, threads, b.m2_lds, b.nm2, &b.grid_mode2);
 }
 
 inline int* tickets_of(const BatchView& b, int kind) {
@@ -1969,8 +2353,12 @@ hipError_t gamma_t(const BatchView& b, int parity, int do_next, const PolarParam
 
 template <int R>
 hipError_t mode2_t(const BatchView& b, int parity, hipStream_t s) {
-  hipLaunchKernelGGL(k_mode2<R>, dim3(b.grid_mode2), dim3(b.m2_threads), b.m2_lds, s, b.desc,
-                     b.m2tiles, b.nm2, tickets_of(b, kTicketMode2), parity, b.m2_hot);
+  if constexpr (kMode2UsesDpp<R>)
+    hipLaunchKernelGGL(k_mode2_dpp<R>, dim3(b.grid_mode2), dim3(b.m2_threads), b.m2_lds, s,
+                       b.desc, b.m2tiles, b.nm2, tickets_of(b, kTicketMode2), parity, b.m2_hot);
+  else
+    hipLaunchKernelGGL(k_mode2<R>, dim3(b.grid_mode2), dim3(b.m2_threads), b.m2_lds, s, b.desc,
+                       b.m2tiles, b.nm2, tickets_of(b, kTicketMode2), parity, b.m2_hot);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || b.m2_hot == 0) return e;
   int rb = (b.m2_hot * R + 255) / 256;
@@ -2116,9 +2504,10 @@ hipError_t run_validate(const int64_t* subj_ptr, const int64_t* row_ptr, const i
 
 hipError_t run_encode(const int64_t* subj_ptr, const int64_t* row_ptr, const int32_t* col,
                       const float* val, int64_t K, int64_t nnz, const int32_t* rank,
-                      uint16_t* rstart, uint16_t* col16, float* val_out, double* nx2,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_encode_rows, dim3(grid1(K)), dim3(256), 0, s, subj_ptr, row_ptr, K, rstart);
+                      uint16_t* rstart, uint16_t* nzrow, uint16_t* col16, float* val_out,
+                      double* nx2, hipStream_t s) {
+  hipLaunchKernelGGL(k_encode_rows, dim3(grid1(K)), dim3(256), 0, s, subj_ptr, row_ptr, K, rstart,
+                     nzrow);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_encode_cols, dim3(grid1(nnz)), dim3(256), 0, s, col, val, nnz, rank, col16,
