@@ -105,14 +105,16 @@ def design_bytes(X, R: int) -> dict:
     """HBM bytes one launch of each per-iteration kernel moves as built: the
     compact encoding of the slices (uint16 column + float32 value per nonzero,
     uint16 row start per row, two int64 offsets per subject), F_k as a float64
-    R x R matrix per subject, W rows and the two V copies."""
+    R x R matrix per subject, W rows and the two V copies; the mode-2 kernel
+    for R <= 16 also reads the uint16 row of each nonzero."""
     K, n_rows, nnz = X.K, X.n_rows, X.nnz
     x = nnz * (2 + 4) + n_rows * 2 + (K + 1) * 16
     f = K * R * R * 8
     w = K * R * 4
     v = X.J * ((R + 3) & ~3) * 4
+    nzrow = nnz * 2 if R <= 16 else 0
     return {"gamma": x + 2 * f + 2 * w + 2 * v,  # F read + written, W and M3 written
-            "mode2": x + f + w + 2 * v,
+            "mode2": x + nzrow + f + w + 2 * v,
             "alpha": x + f + w + v}
 
 
