@@ -47,7 +47,7 @@ def parse():
     p.add_argument("--no-extras", action="store_true",
                    help="default workload only: skip the R=40 iteration, the 64-problem batch "
                         "and the serving trace that the default run adds to its line")
-    p.add_argument("--steps3", type=int, default=3,
+    p.add_argument("--steps3", type=int, default=10,
                    help="timed R=40 iterations in the default run's extras")
     p.add_argument("--copy-bytes", type=int, default=0,
                    help="only run a plain device-to-device copy of this many bytes (calibrates "

@@ -480,6 +480,38 @@ __device__ __forceinline__ void cold_flush(float* M2, const int* qj, const float
   wave_sync();
 }
 
+// Appends the active lanes' cold updates x d (those with `cold`) to the wave's
+// queue, in passes of what the queue has room for; a full queue is added to
+// M2 first.  The count lives in LDS (qcount[0]), where every group of the
+// wave sees it on whichever path it is.
+template <int R, int QN, class DT>
+__device__ __forceinline__ void cold_stage(bool cold, int j, float x, const DT (&d)[R], float* M2,
+                                           int* qcount, int* qj, float* qv) {
+  const uint64_t cm = __ballot(cold);
+  if (cm == 0ull) return;
+  const int ncold = __popcll(cm);
+  const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+  int base = qcount[0];
+  for (int done = 0; done < ncold;) {  // the same on every active lane
+    if (base == QN) {
+      cold_flush<R>(M2, qj, qv, QN);
+      base = 0;
+    }
+    const int take = min(QN - base, ncold - done);
+    if (cold && rank >= done && rank < done + take) {
+      const int slot = base + rank - done;
+      qj[slot] = j;
+#pragma unroll
+      for (int q = 0; q < R; ++q) qv[slot * R + q] = x * (float)d[q];
+    }
+    base += take;
+    done += take;
+  }
+  if (cold && rank == 0) qcount[0] = base;
+  wave_sync();
+}
+
 template <int R>
 __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDesc* __restrict__ P,
                                                           const Tile* __restrict__ T, int ntiles,
@@ -682,32 +714,7 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
               }
               // cold columns: staged in the wave's queue (count in LDS, so
               // that every group of the wave sees it on whichever path it is)
-              const bool cold = act && j >= hot;
-              const uint64_t cm = __ballot(cold);
-              if (cm != 0ull) {
-                const int ncold = __popcll(cm);
-                const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
-                int base = qcount[0];
-                if (base + ncold > QN) {
-                  cold_flush<R>(M2, qj, qv, base);
-                  base = 0;
-                }
-                const int slot = base + rank;
-                if (cold) {
-                  if (slot < QN) {
-                    qj[slot] = j;
-#pragma unroll
-                    for (int q = 0; q < R; ++q) qv[slot * R + q] = x * (float)d[q];
-                  } else {
-                    float* dst = M2 + (size_t)j * LDV;
-#pragma unroll
-                    for (int q = 0; q < R; ++q) gadd(dst + q, x * (float)d[q]);
-                  }
-                }
-                if (cold && rank == 0) qcount[0] = min(QN, base + ncold);
-                wave_sync();
-              }
+              cold_stage<R, QN>(act && j >= hot, j, x, d, M2, qcount, qj, qv);
             }
           }
         }
@@ -960,32 +967,7 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2_dpp(const ProbDesc* __r
         }
         // cold columns: staged in the wave's queue (the count is kept in LDS,
         // where every group of the wave sees it whichever path it is on)
-        const bool cold = ok && j >= hot;
-        const uint64_t cm = __ballot(cold);
-        if (cm != 0ull) {
-          const int ncold = __popcll(cm);
-          const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-              (uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
-          int base = qcount[0];
-          if (base + ncold > QN) {
-            cold_flush<R>(M2, qj, qv, base);
-            base = 0;
-          }
-          const int slot = base + rank;
-          if (cold) {
-            if (slot < QN) {
-              qj[slot] = j;
-#pragma unroll
-              for (int q = 0; q < R; ++q) qv[slot * R + q] = x * (float)d[q];
-            } else {
-              float* dst = M2 + (size_t)j * LDV;
-#pragma unroll
-              for (int q = 0; q < R; ++q) gadd(dst + q, x * (float)d[q]);
-            }
-          }
-          if (cold && rank == 0) qcount[0] = min(QN, base + ncold);
-          wave_sync();
-        }
+        cold_stage<R, QN>(ok && j >= hot, j, x, d, M2, qcount, qj, qv);
         }
       }
     }
