@@ -136,9 +136,9 @@ typedef struct {
                             non-negative least squares on the same normal
                             equations (the constraints of the paper's
                             experiments, Sec. "Classical Algorithm for PARAFAC2"
-                            and Sec. "Setup"); H stays unconstrained.  The
-                            next Procrustes step is then not fused into the
-                            mode-3 pass (one more pass over X per iteration);
+                            and Sec. "Setup"); H stays unconstrained.  The W
+                            rows are solved inside the mode-3 pass, which
+                            still takes the next Procrustes step;
                             0: unconstrained                                  */
   int32_t baseline;      /* 1: run the paper's comparison method instead of
                             SPARTan's MTTKRPs ("Sparse PARAFAC2", Sec. "Setup"):

@@ -56,7 +56,6 @@ struct ProbDesc {
   int32_t hot;      // mode-2 hot columns of this problem
   const int32_t* order;  // subject at each position of the per-subject passes, or
                          // nullptr for the natural order
-  double* M3d;      // K x R float64 copy of M3 (rows for the non-negative W update), or nullptr
   int32_t nonneg;   // 1: V and W (the diagonals of S_k) are updated by NNLS
   const int32_t* econ;  // the subjects with I_k < R (n_econ of them)
   int64_t n_econ;

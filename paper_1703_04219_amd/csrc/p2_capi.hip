@@ -89,7 +89,7 @@ int64_t mode2_parts(int64_t K, int R, int cap) {
 
 // Offsets of every piece of the context workspace.
 struct Plan {
-  size_t zbase, rbase, rstart, nzrow, col16, val, rank, perm, hist, order, econ, V[2], F, M2, M3, M3d, E,
+  size_t zbase, rbase, rstart, nzrow, col16, val, rank, perm, hist, order, econ, V[2], F, M2, M3, E,
       small, err, part, desc, tiles, m2tiles, tickets, iter, erow, eval, runs, runbase, Q, yr, yj,
       yk, yv, acc, total;
   bool baseline = false;  // explicit-Y comparison method: runs, Q and Y are planned
@@ -131,7 +131,6 @@ Plan make_plan(int64_t K, int64_t J, int64_t n_rows, int64_t nnz, int R, const p
   p.M2 = take(sizeof(float) * J * LDV);
   p.M3 = take(sizeof(float) * (size_t)K * R);
   p.nonneg = o && o->nonneg;
-  p.M3d = p.nonneg ? take(sizeof(double) * (size_t)K * R) : 0;
   p.warm = (o && o->keep_bases) && p2::warm_supported(R);
   const int64_t NC = (R & 1) ? R + 1 : R;
   p.E = p.warm ? take(sizeof(float) * (size_t)K * NC * R) : 0;
@@ -256,7 +255,6 @@ struct parafac2_ctx {
     d.nparts = 0;  // set by the runner from its schedule
     d.hot = hot;
     d.order = at<int32_t>(plan.order);
-    d.M3d = plan.nonneg ? at<double>(plan.M3d) : nullptr;
     d.nonneg = plan.nonneg ? 1 : 0;
     d.econ = at<int32_t>(plan.econ);
     d.n_econ = n_econ;
@@ -292,7 +290,6 @@ struct Runner {
   hipStream_t cap = nullptr;  // capture stream of the graphs
   hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   bool planned = false;
-  bool any_nonneg = false;
   bool any_econ = false;
   bool baseline = false;  // a context of one running the explicit-Y method
   // profiling: event pairs per phase, resolved lazily
@@ -435,6 +432,7 @@ int runner_plan(Runner& r) {
     b.tickets = g.tickets;
     b.dynamic = r.sched.dynamic;
     b.warm = warm ? 1 : 0;
+    b.nonneg = g.nonneg ? 1 : 0;
     b.max_hot = max_hot;
     b.m2_threads = r.sched.m2_threads;
     b.m2_blocks = r.sched.m2_blocks;
@@ -498,13 +496,12 @@ int runner_body(Runner& r, int parity, int do_next, hipStream_t s, bool prof) {
     // mode 2 -> V
     PHASE(P2_PHASE_MODE2, HIP_TRY(p2::run_mode2(b, parity, s)));
     PHASE(P2_PHASE_VUPDATE, HIP_TRY(p2::run_vupdate(b, parity, s));
-          if (g.nonneg) HIP_TRY(p2::run_nnls(b, 0, parity, s));
+          if (g.nonneg) HIP_TRY(p2::run_nnls(b, parity, s));
           HIP_TRY(p2::run_gram(b, 1, parity, s)); HIP_TRY(p2::run_solve_n3(b, g.pp, s));
           HIP_TRY(p2::run_vscale(b, parity, s)));
     // mode 3 -> W, fit (+ next Procrustes step)
     if (do_next) HIP_TRY(p2::run_zero(b, 1, s));
     PHASE(P2_PHASE_GAMMA, HIP_TRY(p2::run_gamma(b, parity, do_next, g.pp, s));
-          if (g.nonneg) HIP_TRY(p2::run_nnls(b, 1, parity, s));
           if (g.econ) HIP_TRY(p2::run_econ_fit(b, parity, s)));
     PHASE(P2_PHASE_FIT, HIP_TRY(p2::run_fit(b, s)));
   }
@@ -589,7 +586,7 @@ int runner_iterate_n(Runner& r, int32_t n, double* fit_host, double* loss_host) 
     // the non-negative W rows are solved after the mode-3 pass, and the loss
     // terms of subjects with I_k < R need this iteration's F_k after it, so
     // in either case the next Procrustes step cannot be fused into that pass
-    const int do_next = (it + 1 < n && !r.any_nonneg && !r.any_econ && !r.baseline) ? 1 : 0;
+    const int do_next = (it + 1 < n && !r.any_econ && !r.baseline) ? 1 : 0;
     if (r.baseline) {
       P2_TRY(runner_body_baseline(r, parity, s, prof));
     } else if (graph) {
@@ -827,7 +824,6 @@ int runner_make(Runner** out, parafac2_ctx* const* ctxs, int n, const RunnerLayo
       g.nonneg = g.nonneg || ctxs[i]->plan.nonneg;
       g.econ = g.econ || ctxs[i]->n_econ > 0;
     }
-    r->any_nonneg = r->any_nonneg || g.nonneg;
     r->any_econ = r->any_econ || g.econ;
     for (int i : lg.members) r->baseline = r->baseline || ctxs[i]->plan.baseline;
     r->groups.push_back(g);

@@ -42,6 +42,7 @@ struct BatchView {
   int dynamic = 0;
   int warm = 0;                    // warm-started polar (every problem has its basis E);
                                    // plan_launch clears it for ranks built without it
+  int nonneg = 0;                  // some problem updates V and W by NNLS
   int max_hot = 0;                 // hot columns planned by the problems (max over them)
   int64_t maxK = 0, maxJ = 0;
   int64_t maxEcon = 0;             // most subjects with I_k < R in one problem
@@ -70,9 +71,9 @@ hipError_t run_mode2(const BatchView& b, int parity, hipStream_t s);
 hipError_t run_gram(const BatchView& b, int which, int parity, hipStream_t s);
 hipError_t run_solve_h(const BatchView& b, const PolarParams& pp, hipStream_t s);
 hipError_t run_vupdate(const BatchView& b, int parity, hipStream_t s);
-// Non-negative rows of the problems with the constraint: which = 0 V_{t+1}
-// (instead of run_vupdate), 1 W with the fit terms (after run_gamma).
-hipError_t run_nnls(const BatchView& b, int which, int parity, hipStream_t s);
+// Non-negative V_{t+1} rows of the problems with the constraint (instead of
+// run_vupdate); their W rows are solved in run_gamma.
+hipError_t run_nnls(const BatchView& b, int parity, hipStream_t s);
 // Loss terms of the subjects with I_k < R (after the W update).
 hipError_t run_econ_fit(const BatchView& b, int parity, hipStream_t s);
 hipError_t run_solve_n3(const BatchView& b, const PolarParams& pp, hipStream_t s);

@@ -86,12 +86,19 @@ struct PolarLds {
   static constexpr int kAf = (CH * (R + LDV) + 1) / 2;
   static constexpr int kA = kAf > CH * R ? kAf : CH * R;
   static constexpr int kB = R * R + NC * R;
-  static constexpr int kRegion = kA > kB ? kA : kB;
+  // the non-negative W row solve in gamma uses the region once the mode-3 row
+  // is formed (its factor, right-hand side and reductions)
+  static constexpr int kNnls = R * R + R + 3 * NC;
+  static constexpr int kRegion = kA > kB ? (kA > kNnls ? kA : kNnls) : (kB > kNnls ? kB : kNnls);
   // minimum waves per SIMD in k_gamma's launch bound: none asked for.  At
   // R = 10 the kernel fits three waves by itself (163 VGPRs without warm
   // starts; two waves cost about 0.6 ms per launch of the K = 1M pass), and a
   // bound asking for three changed its schedule and cost about 0.2 ms
   static constexpr int kMinWaves = 1;
+  // with the W row's NNLS in the kernel (non-negative problems) R = 10 needs
+  // about 200 VGPRs; bounded to three waves it spills 92 bytes per lane and
+  // runs 10 % faster (5.53 against 6.16 ms per pass at K = 1M)
+  static constexpr int kMinWavesNN = R == 10 ? 3 : 1;
   static constexpr int kPerGroup = kRegion + 2 * R + NC;
   static_assert(R % 2 == 1 || (kPerGroup % 2 == 0 && (CH * R) % 4 == 0),
                 "even-R group regions and the FP32 A' rows must stay 16-byte aligned");
@@ -240,15 +247,223 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
 }
 
 // ---------------------------------------------------------------------------
+// Non-negative least squares per row: the non-negative V and S_k of the
+// paper's experiments (Sec. "Classical Algorithm for PARAFAC2" and Sec.
+// "Setup", where the fast NNLS of Bro and De Jong is used).  For one row m of
+// an MTTKRP and the R x R normal matrix N of its update, x = argmin over
+// x >= 0 of the least-squares problem whose normal equations are N x = m, by
+// the active-set method on the cross products N, m:
+//   x = 0; w = m - N x
+//   while the largest w_j off the passive set P exceeds tol: j joins P;
+//     s = solution of N[P,P] s_P = m_P (0 off P);
+//     while some s_j <= 0 on P: step x towards s until the first such x_j
+//       reaches 0, drop the variables at 0 from P, solve again;
+//     x = s; w = m - N x.
+// One group of NC lanes per row, lane c owns x_c and column c of N (N is
+// symmetric).  Reductions over the group (largest gradient, smallest step,
+// largest |x|) go through LDS and take the first index on ties.  The passive
+// block is solved by a Cholesky factorisation of N with the rows and columns
+// off P replaced by those of the identity, column c per lane, factor columns
+// broadcast through LDS.
+// ---------------------------------------------------------------------------
+template <int R>
+struct NnlsLds {
+  static constexpr int NC = Geo<R>::NC;
+  // L (R x R, factor column k at k * R), v (R), xs (NC), pf (NC), red (NC)
+  static constexpr int kPerGroup = R * R + R + 3 * NC;
+};
+
+// Group reductions over lanes 0..R-1 of one value per lane: largest value
+// (first index on ties) or smallest value (first index on ties).
+template <int R>
+__device__ __forceinline__ void group_argmax(double* red, double v, int c, double& best, int& at) {
+  if (c < R) red[c] = v;
+  wave_sync();
+  best = red[0];
+  at = 0;
+  for (int i = 1; i < R; ++i) {
+    const double t = red[i];
+    if (t > best) {
+      best = t;
+      at = i;
+    }
+  }
+  wave_sync();
+}
+
+template <int R>
+__device__ __forceinline__ void group_argmin(double* red, double v, int c, double& best, int& at) {
+  if (c < R) red[c] = v;
+  wave_sync();
+  best = red[0];
+  at = 0;
+  for (int i = 1; i < R; ++i) {
+    const double t = red[i];
+    if (t < best) {
+      best = t;
+      at = i;
+    }
+  }
+  wave_sync();
+}
+
+// s_c of the solution of N[P,P] s_P = m_P (s = 0 off P) for the group.
+template <int R>
+__device__ double nnls_solve(const double (&ncol)[R], double m, bool p, int c, double* L,
+                             double* v, double* pf) {
+  const bool real = c < R;
+  if (real) pf[c] = p ? 1.0 : 0.0;
+  wave_sync();
+  double g[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) g[i] = (p && pf[i] != 0.0) ? ncol[i] : (i == c ? 1.0 : 0.0);
+#pragma nounroll
+  for (int k = 0; k < R; ++k) {
+    if (c == k) {
+      const double piv = g[k];
+      const double rs = piv > 0.0 ? 1.0 / sqrt(piv) : 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        g[i] *= rs;
+        L[k * R + i] = g[i];
+      }
+    }
+    wave_sync();
+    if (real && c > k) {
+      const double lck = L[k * R + c];
+#pragma unroll
+      for (int i = 0; i < R; ++i) g[i] = fma(-lck, L[k * R + i], g[i]);
+    }
+    wave_sync();
+  }
+  if (real) v[c] = p ? m : 0.0;
+  wave_sync();
+#pragma nounroll
+  for (int k = 0; k < R; ++k) {  // L y = m_P
+    if (c == k) {
+      const double d = L[k * R + k];
+      v[k] = d > 0.0 ? v[k] / d : 0.0;
+    }
+    wave_sync();
+    if (real && c > k) v[c] = fma(-L[k * R + c], v[k], v[c]);
+    wave_sync();
+  }
+#pragma nounroll
+  for (int k = R - 1; k >= 0; --k) {  // L^T s = y
+    if (c == k) {
+      const double d = L[k * R + k];
+      v[k] = d > 0.0 ? v[k] / d : 0.0;
+    }
+    wave_sync();
+    if (real && c < k) v[c] = fma(-L[c * R + k], v[k], v[c]);
+    wave_sync();
+  }
+  const double sc = (real && p) ? v[c] : 0.0;
+  wave_sync();
+  return sc;
+}
+
+// x_c of the NNLS solution for the group's row (m = m_c of lane c).  warm:
+// lane c's variable was positive in the previous iteration's row; if solving
+// on that support gives a positive solution, the method starts from it (a
+// feasible point with x > 0 exactly on P, from which the steps above apply
+// unchanged), else from x = 0.  N is positive definite, so the solution is
+// unique and does not depend on the starting point.
+template <int R>
+__device__ double nnls_group(const double (&ncol)[R], double m, int c, double* buf, bool warm) {
+  constexpr int NC = Geo<R>::NC;
+  constexpr double eps = 2.220446049250313e-16;
+  const double inf = __builtin_huge_val();
+  double* L = buf;
+  double* v = L + R * R;
+  double* xs = v + R;
+  double* pf = xs + NC;
+  double* red = pf + NC;
+  const bool real = c < R;
+  double x = 0.0;
+  bool p = false, blocked = false;
+  double scale, tmp;
+  int at;
+  group_argmax<R>(red, real ? fabs(m) : 0.0, c, scale, at);
+  scale = fmax(scale, 2.2250738585072014e-308);
+  double tol = 10.0 * R * eps * scale;
+  double w = m;
+  double any_warm;
+  group_argmax<R>(red, (real && warm) ? 1.0 : 0.0, c, any_warm, at);
+  if (any_warm > 0.0) {
+    const bool pw = real && warm;
+    const double s = nnls_solve<R>(ncol, m, pw, c, L, v, pf);
+    double smin;
+    group_argmin<R>(red, pw ? s : __builtin_huge_val(), c, smin, at);
+    if (smin > 0.0) {
+      p = pw;
+      x = s;
+      if (real) xs[c] = x;
+      wave_sync();
+      double nx = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) nx = fma(ncol[i], xs[i], nx);
+      wave_sync();
+      w = m - nx;
+      group_argmax<R>(red, real ? fabs(nx) : 0.0, c, tmp, at);
+      scale = fmax(scale, tmp);
+      tol = 10.0 * R * eps * scale;
+    }
+  }
+  for (int outer = 0; outer < 3 * R; ++outer) {
+    double best;
+    int j;
+    group_argmax<R>(red, (real && !p && !blocked) ? w : -inf, c, best, j);
+    if (!(best > tol)) break;
+    if (c == j) p = true;
+    double s = nnls_solve<R>(ncol, m, p, c, L, v, pf);
+    for (int inner = 0; inner <= R; ++inner) {
+      const bool bad = p && s <= 0.0;
+      const double d = x - s;
+      double alpha;
+      int q;
+      group_argmin<R>(red, bad ? (d > 0.0 ? x / d : 0.0) : inf, c, alpha, q);
+      if (alpha == inf) break;
+      x = fma(alpha, s - x, x);
+      if (c == q) x = 0.0;  // the variable that limits the step reaches zero
+      double xm;
+      group_argmax<R>(red, real ? fabs(x) : 0.0, c, xm, at);
+      if (p && x <= 10.0 * eps * fmax(xm, 1e-300)) p = false;
+      if (!p) x = 0.0;
+      if (alpha > 0.0)
+        blocked = false;
+      else if (c == j && !p)
+        blocked = true;  // rounding: w_j > tol but its solve was <= 0
+      s = nnls_solve<R>(ncol, m, p, c, L, v, pf);
+    }
+    x = s;
+    if (real) xs[c] = x;
+    wave_sync();
+    double nx = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) nx = fma(ncol[i], xs[i], nx);
+    wave_sync();
+    w = m - nx;
+    group_argmax<R>(red, real ? fabs(nx) : 0.0, c, tmp, at);
+    scale = fmax(scale, tmp);
+    tol = 10.0 * R * eps * scale;
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------------------
 // k_gamma: mode-3 MTTKRP row per subject (equation (mttkrp3_row_wise)) from
 // A_k = X_k V_t and A'_k = X_k V_{t+1}: (Y_k V_{t+1}) = F_k A_k^T A'_k,
 // m3(c) = H(:, c) . (Y_k V_{t+1})(:, c); the W row update
 // w = m3 ((V^T V) * (H^T H))^+ (Algorithm "CP-ALS"); the loss terms; and, if
 // do_next, the next iteration's Procrustes step and mode-1 partial from
-// C'_k = A'_k^T A'_k.
+// C'_k = A'_k^T A'_k.  With NN (a launch with problems under the
+// non-negativity constraint) the W row of such problems is the NNLS solution
+// of N3 w = m3 instead, formed in the group before the Procrustes step, so
+// that the next step stays fused into this pass.
 // ---------------------------------------------------------------------------
-template <int R, bool WARM>
-__global__ void __launch_bounds__(256, PolarLds<R>::kMinWaves) k_gamma(const ProbDesc* __restrict__ P,
+template <int R, bool WARM, bool NN>
+__global__ void __launch_bounds__(256, NN ? PolarLds<R>::kMinWavesNN : PolarLds<R>::kMinWaves) k_gamma(const ProbDesc* __restrict__ P,
                                                 const Tile* __restrict__ T, int ntiles,
                                                 int* tickets, int parity, int do_next,
                                                 PolarParams pp) {
@@ -290,7 +505,6 @@ __global__ void __launch_bounds__(256, PolarLds<R>::kMinWaves) k_gamma(const Pro
     float* __restrict__ W = D.W;
     double* __restrict__ F = D.F;
     float* __restrict__ M3 = D.M3;
-    double* __restrict__ M3d = D.nonneg ? D.M3d : nullptr;
     __syncthreads();
     load_shared_rxr<R>(Hs, D.H);
     load_shared_rxr<R>(N3s, D.small + SL.N3);
@@ -340,17 +554,25 @@ __global__ void __launch_bounds__(256, PolarLds<R>::kMinWaves) k_gamma(const Pro
         if (real) mv[c] = m3;
         wave_sync();
         double wn = 0.0;
+        if (NN && D.nonneg) {
+          // NNLS from the float64 row, started from the support of W_t's row;
+          // the region (F and P above) is free again
+          double ncol[R];
 #pragma unroll
-        for (int l = 0; l < R; ++l) wn = fma(mv[l], N3ps[l * R + cc], wn);
+          for (int i = 0; i < R; ++i) ncol[i] = N3s[i * R + cc];
+          const bool warm = real && glob(W)[k * R + c] > 0.f;
+          wn = nnls_group<R>(ncol, m3, c, region, warm);
+        } else {
+#pragma unroll
+          for (int l = 0; l < R; ++l) wn = fma(mv[l], N3ps[l * R + cc], wn);
+        }
         if (real) {
           glob(W)[k * R + c] = (float)wn;
           glob(M3)[k * R + c] = (float)m3;
           wv[c] = (double)(float)wn;
-          // the non-negative W update (k_nnls_rows) starts from the float64 row
-          if (M3d) glob(M3d)[k * R + c] = m3;
         }
         wave_sync();
-        if (real && !M3d) {
+        if (real) {
           const double wf = wv[c];
           double tt = 0.0;
 #pragma unroll
@@ -1200,234 +1422,23 @@ __global__ void __launch_bounds__(256) k_vupdate(const ProbDesc* __restrict__ P,
   }
 }
 
-// ---------------------------------------------------------------------------
-// Non-negative least squares per row: the non-negative V and S_k of the
-// paper's experiments (Sec. "Classical Algorithm for PARAFAC2" and Sec.
-// "Setup", where the fast NNLS of Bro and De Jong is used).  For one row m of
-// an MTTKRP and the R x R normal matrix N of its update, x = argmin over
-// x >= 0 of the least-squares problem whose normal equations are N x = m, by
-// the active-set method on the cross products N, m:
-//   x = 0; w = m - N x
-//   while the largest w_j off the passive set P exceeds tol: j joins P;
-//     s = solution of N[P,P] s_P = m_P (0 off P);
-//     while some s_j <= 0 on P: step x towards s until the first such x_j
-//       reaches 0, drop the variables at 0 from P, solve again;
-//     x = s; w = m - N x.
-// One group of NC lanes per row, lane c owns x_c and column c of N (N is
-// symmetric).  Reductions over the group (largest gradient, smallest step,
-// largest |x|) go through LDS and take the first index on ties.  The passive
-// block is solved by a Cholesky factorisation of N with the rows and columns
-// off P replaced by those of the identity, column c per lane, factor columns
-// broadcast through LDS.
-// ---------------------------------------------------------------------------
+// V_{t+1} rows = NNLS((W^T W) * (H^T H), M2 rows) (replaces k_vupdate for the
+// problems under the non-negativity constraint; the others are skipped; the W
+// rows are solved in k_gamma).  grid.y = problem.
 template <int R>
-struct NnlsLds {
-  static constexpr int NC = Geo<R>::NC;
-  // L (R x R, factor column k at k * R), v (R), xs (NC), pf (NC), red (NC)
-  static constexpr int kPerGroup = R * R + R + 3 * NC;
-};
-
-// Group reductions over lanes 0..R-1 of one value per lane: largest value
-// (first index on ties) or smallest value (first index on ties).
-template <int R>
-__device__ __forceinline__ void group_argmax(double* red, double v, int c, double& best, int& at) {
-  if (c < R) red[c] = v;
-  wave_sync();
-  best = red[0];
-  at = 0;
-  for (int i = 1; i < R; ++i) {
-    const double t = red[i];
-    if (t > best) {
-      best = t;
-      at = i;
-    }
-  }
-  wave_sync();
-}
-
-template <int R>
-__device__ __forceinline__ void group_argmin(double* red, double v, int c, double& best, int& at) {
-  if (c < R) red[c] = v;
-  wave_sync();
-  best = red[0];
-  at = 0;
-  for (int i = 1; i < R; ++i) {
-    const double t = red[i];
-    if (t < best) {
-      best = t;
-      at = i;
-    }
-  }
-  wave_sync();
-}
-
-// s_c of the solution of N[P,P] s_P = m_P (s = 0 off P) for the group.
-template <int R>
-__device__ double nnls_solve(const double (&ncol)[R], double m, bool p, int c, double* L,
-                             double* v, double* pf) {
-  const bool real = c < R;
-  if (real) pf[c] = p ? 1.0 : 0.0;
-  wave_sync();
-  double g[R];
-#pragma unroll
-  for (int i = 0; i < R; ++i) g[i] = (p && pf[i] != 0.0) ? ncol[i] : (i == c ? 1.0 : 0.0);
-#pragma nounroll
-  for (int k = 0; k < R; ++k) {
-    if (c == k) {
-      const double piv = g[k];
-      const double rs = piv > 0.0 ? 1.0 / sqrt(piv) : 0.0;
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        g[i] *= rs;
-        L[k * R + i] = g[i];
-      }
-    }
-    wave_sync();
-    if (real && c > k) {
-      const double lck = L[k * R + c];
-#pragma unroll
-      for (int i = 0; i < R; ++i) g[i] = fma(-lck, L[k * R + i], g[i]);
-    }
-    wave_sync();
-  }
-  if (real) v[c] = p ? m : 0.0;
-  wave_sync();
-#pragma nounroll
-  for (int k = 0; k < R; ++k) {  // L y = m_P
-    if (c == k) {
-      const double d = L[k * R + k];
-      v[k] = d > 0.0 ? v[k] / d : 0.0;
-    }
-    wave_sync();
-    if (real && c > k) v[c] = fma(-L[k * R + c], v[k], v[c]);
-    wave_sync();
-  }
-#pragma nounroll
-  for (int k = R - 1; k >= 0; --k) {  // L^T s = y
-    if (c == k) {
-      const double d = L[k * R + k];
-      v[k] = d > 0.0 ? v[k] / d : 0.0;
-    }
-    wave_sync();
-    if (real && c < k) v[c] = fma(-L[c * R + k], v[k], v[c]);
-    wave_sync();
-  }
-  const double sc = (real && p) ? v[c] : 0.0;
-  wave_sync();
-  return sc;
-}
-
-// x_c of the NNLS solution for the group's row (m = m_c of lane c).  warm:
-// lane c's variable was positive in the previous iteration's row; if solving
-// on that support gives a positive solution, the method starts from it (a
-// feasible point with x > 0 exactly on P, from which the steps above apply
-// unchanged), else from x = 0.  N is positive definite, so the solution is
-// unique and does not depend on the starting point.
-template <int R>
-__device__ double nnls_group(const double (&ncol)[R], double m, int c, double* buf, bool warm) {
-  constexpr int NC = Geo<R>::NC;
-  constexpr double eps = 2.220446049250313e-16;
-  const double inf = __builtin_huge_val();
-  double* L = buf;
-  double* v = L + R * R;
-  double* xs = v + R;
-  double* pf = xs + NC;
-  double* red = pf + NC;
-  const bool real = c < R;
-  double x = 0.0;
-  bool p = false, blocked = false;
-  double scale, tmp;
-  int at;
-  group_argmax<R>(red, real ? fabs(m) : 0.0, c, scale, at);
-  scale = fmax(scale, 2.2250738585072014e-308);
-  double tol = 10.0 * R * eps * scale;
-  double w = m;
-  double any_warm;
-  group_argmax<R>(red, (real && warm) ? 1.0 : 0.0, c, any_warm, at);
-  if (any_warm > 0.0) {
-    const bool pw = real && warm;
-    const double s = nnls_solve<R>(ncol, m, pw, c, L, v, pf);
-    double smin;
-    group_argmin<R>(red, pw ? s : __builtin_huge_val(), c, smin, at);
-    if (smin > 0.0) {
-      p = pw;
-      x = s;
-      if (real) xs[c] = x;
-      wave_sync();
-      double nx = 0.0;
-#pragma unroll
-      for (int i = 0; i < R; ++i) nx = fma(ncol[i], xs[i], nx);
-      wave_sync();
-      w = m - nx;
-      group_argmax<R>(red, real ? fabs(nx) : 0.0, c, tmp, at);
-      scale = fmax(scale, tmp);
-      tol = 10.0 * R * eps * scale;
-    }
-  }
-  for (int outer = 0; outer < 3 * R; ++outer) {
-    double best;
-    int j;
-    group_argmax<R>(red, (real && !p && !blocked) ? w : -inf, c, best, j);
-    if (!(best > tol)) break;
-    if (c == j) p = true;
-    double s = nnls_solve<R>(ncol, m, p, c, L, v, pf);
-    for (int inner = 0; inner <= R; ++inner) {
-      const bool bad = p && s <= 0.0;
-      const double d = x - s;
-      double alpha;
-      int q;
-      group_argmin<R>(red, bad ? (d > 0.0 ? x / d : 0.0) : inf, c, alpha, q);
-      if (alpha == inf) break;
-      x = fma(alpha, s - x, x);
-      if (c == q) x = 0.0;  // the variable that limits the step reaches zero
-      double xm;
-      group_argmax<R>(red, real ? fabs(x) : 0.0, c, xm, at);
-      if (p && x <= 10.0 * eps * fmax(xm, 1e-300)) p = false;
-      if (!p) x = 0.0;
-      if (alpha > 0.0)
-        blocked = false;
-      else if (c == j && !p)
-        blocked = true;  // rounding: w_j > tol but its solve was <= 0
-      s = nnls_solve<R>(ncol, m, p, c, L, v, pf);
-    }
-    x = s;
-    if (real) xs[c] = x;
-    wave_sync();
-    double nx = 0.0;
-#pragma unroll
-    for (int i = 0; i < R; ++i) nx = fma(ncol[i], xs[i], nx);
-    wave_sync();
-    w = m - nx;
-    group_argmax<R>(red, real ? fabs(nx) : 0.0, c, tmp, at);
-    scale = fmax(scale, tmp);
-    tol = 10.0 * R * eps * scale;
-  }
-  return x;
-}
-
-// which = 0: V_{t+1} rows = NNLS((W^T W) * (H^T H), M2 rows) (replaces
-// k_vupdate); which = 1: W rows = NNLS(N3, M3 rows, from the float64 copy of
-// M3), and the fit terms <W, M3> and W N3 W^T.  Problems without the
-// constraint are skipped.  grid.y = problem.
-template <int R>
-__global__ void __launch_bounds__(256) k_nnls_rows(const ProbDesc* __restrict__ P, int which,
-                                                    int parity) {
-  constexpr int NC = Geo<R>::NC;
+__global__ void __launch_bounds__(256) k_nnls_rows(const ProbDesc* __restrict__ P, int parity) {
   constexpr int GPW = Geo<R>::GPW;
   constexpr int LDV = Geo<R>::LDV;
   constexpr SmallLayout SL = small_layout(R);
   const ProbDesc& D = P[blockIdx.y];
   if (!D.nonneg) return;
-  double* Ns = reinterpret_cast<double*>(p2_smem);  // N (R x R), then the fit partials
-  double* shFit = Ns + R * R;
+  double* Ns = reinterpret_cast<double*>(p2_smem);  // N (R x R)
   const Lane L = lane_info<R>();
   const int wave = threadIdx.x / kWave;
   const int gpb = (blockDim.x / kWave) * GPW;
-  double* buf = shFit + 2 + (wave * GPW + (L.live ? L.grp : 0)) * NnlsLds<R>::kPerGroup;
+  double* buf = Ns + R * R + (wave * GPW + (L.live ? L.grp : 0)) * NnlsLds<R>::kPerGroup;
   const P2_GLOBAL double* sm = glob(D.small);
-  for (int q = threadIdx.x; q < R * R; q += blockDim.x)
-    Ns[q] = which == 0 ? sm[SL.WtW + q] * sm[SL.HtH + q] : sm[SL.N3 + q];
-  if (threadIdx.x < 2) shFit[threadIdx.x] = 0.0;
+  for (int q = threadIdx.x; q < R * R; q += blockDim.x) Ns[q] = sm[SL.WtW + q] * sm[SL.HtH + q];
   __syncthreads();
   const int c = L.j;
   const bool real = c < R;
@@ -1435,50 +1446,14 @@ __global__ void __launch_bounds__(256) k_nnls_rows(const ProbDesc* __restrict__ 
   double ncol[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) ncol[i] = Ns[i * R + cc];
-  const int64_t n = which == 0 ? D.J : D.K;
-  double fa = 0.0, fb = 0.0;
   if (L.live) {
     const int64_t stride = (int64_t)gridDim.x * gpb;
-    for (int64_t r = (int64_t)blockIdx.x * gpb + wave * GPW + L.grp; r < n; r += stride) {
-      const double m = !real ? 0.0
-                       : which == 0 ? (double)glob(D.M2)[r * LDV + c]
-                                    : glob(D.M3d)[r * R + c];
-      // the previous iteration's row (V_t or W_t) gives the starting support
-      const bool warm = real && (which == 0 ? glob(D.V[parity])[r * LDV + c]
-                                            : glob(D.W)[r * R + c]) > 0.f;
+    for (int64_t r = (int64_t)blockIdx.x * gpb + wave * GPW + L.grp; r < D.J; r += stride) {
+      const double m = real ? (double)glob(D.M2)[r * LDV + c] : 0.0;
+      // the previous iteration's row gives the starting support
+      const bool warm = real && glob(D.V[parity])[r * LDV + c] > 0.f;
       const double x = nnls_group<R>(ncol, m, c, buf, warm);
-      if (which == 0) {
-        if (real) glob(D.V[parity ^ 1])[r * LDV + c] = (float)x;
-      } else {
-        // fit terms from the stored (float) W row, as in the unconstrained path
-        const double xf = (double)(float)x;
-        double* xs = buf + R * R + R;
-        if (real) {
-          glob(D.W)[r * R + c] = (float)x;
-          glob(D.M3)[r * R + c] = (float)m;
-          xs[c] = xf;
-        }
-        wave_sync();
-        double nx = 0.0;
-#pragma unroll
-        for (int i = 0; i < R; ++i) nx = fma(ncol[i], xs[i], nx);
-        wave_sync();
-        if (real) {
-          fa = fma(xf, m, fa);
-          fb = fma(xf, nx, fb);
-        }
-      }
-    }
-  }
-  if (which == 1) {
-    if (L.live && real) {
-      atomicAdd(&shFit[0], fa);
-      atomicAdd(&shFit[1], fb);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      gadd(D.small + SL.fitacc + 0, shFit[0]);
-      gadd(D.small + SL.fitacc + 1, shFit[1]);
+      if (real) glob(D.V[parity ^ 1])[r * LDV + c] = (float)x;
     }
   }
 }
@@ -2259,8 +2234,10 @@ hipError_t plan_t(BatchView& b) {
       e = resident_grid(k_alpha<R, true>, alpha_threads<R>(), alpha_lds<R>(), b.ntiles,
                         &b.grid_alpha);
       if (e != hipSuccess) return e;
-      e = resident_grid(k_gamma<R, true>, gamma_threads<R>(), gamma_lds<R>(), b.ntiles,
-                        &b.grid_gamma);
+      e = b.nonneg ? resident_grid(k_gamma<R, true, true>, gamma_threads<R>(), gamma_lds<R>(),
+                                   b.ntiles, &b.grid_gamma)
+                   : resident_grid(k_gamma<R, true, false>, gamma_threads<R>(), gamma_lds<R>(),
+                                   b.ntiles, &b.grid_gamma);
       if (e != hipSuccess) return e;
     }
   }
@@ -2268,8 +2245,10 @@ hipError_t plan_t(BatchView& b) {
     e = resident_grid(k_alpha<R, false>, alpha_threads<R>(), alpha_lds<R>(), b.ntiles,
                       &b.grid_alpha);
     if (e != hipSuccess) return e;
-    e = resident_grid(k_gamma<R, false>, gamma_threads<R>(), gamma_lds<R>(), b.ntiles,
-                      &b.grid_gamma);
+    e = b.nonneg ? resident_grid(k_gamma<R, false, true>, gamma_threads<R>(), gamma_lds<R>(),
+                                 b.ntiles, &b.grid_gamma)
+                 : resident_grid(k_gamma<R, false, false>, gamma_threads<R>(), gamma_lds<R>(),
+                                 b.ntiles, &b.grid_gamma);
     if (e != hipSuccess) return e;
   }
   // mode 2: blocks of m2_threads (0 = the rank's default) with m2_blocks of
@@ -2310,9 +2289,14 @@ hipError_t alpha_w(const BatchView& b, int parity, const PolarParams& pp, hipStr
 template <int R, bool WARM>
 hipError_t gamma_w(const BatchView& b, int parity, int do_next, const PolarParams& pp,
                    hipStream_t s) {
-  hipLaunchKernelGGL((k_gamma<R, WARM>), dim3(b.grid_gamma), dim3(gamma_threads<R>()),
-                     gamma_lds<R>(), s, b.desc, b.tiles, b.ntiles, tickets_of(b, kTicketGamma),
-                     parity, do_next, pp);
+  if (b.nonneg)
+    hipLaunchKernelGGL((k_gamma<R, WARM, true>), dim3(b.grid_gamma), dim3(gamma_threads<R>()),
+                       gamma_lds<R>(), s, b.desc, b.tiles, b.ntiles,
+                       tickets_of(b, kTicketGamma), parity, do_next, pp);
+  else
+    hipLaunchKernelGGL((k_gamma<R, WARM, false>), dim3(b.grid_gamma), dim3(gamma_threads<R>()),
+                       gamma_lds<R>(), s, b.desc, b.tiles, b.ntiles,
+                       tickets_of(b, kTicketGamma), parity, do_next, pp);
   return hipGetLastError();
 }
 
@@ -2597,16 +2581,15 @@ hipError_t run_vupdate(const BatchView& b, int parity, hipStream_t s) {
 }
 
 template <int R>
-hipError_t nnls_t(const BatchView& b, int which, int parity, hipStream_t s) {
+hipError_t nnls_t(const BatchView& b, int parity, hipStream_t s) {
   constexpr int T = 256;
   constexpr int gpb = (T / kWave) * Geo<R>::GPW;
-  constexpr size_t lds = sizeof(double) * (R * R + 2 + gpb * NnlsLds<R>::kPerGroup);
+  constexpr size_t lds = sizeof(double) * (R * R + gpb * NnlsLds<R>::kPerGroup);
   static_assert(lds <= kLdsBudget, "NNLS LDS plan");
   hipError_t e = allow_lds(k_nnls_rows<R>, lds);
   if (e != hipSuccess) return e;
-  const int64_t rows = which == 0 ? b.maxJ : b.maxK;
-  const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((rows + gpb - 1) / gpb, 8192));
-  hipLaunchKernelGGL(k_nnls_rows<R>, dim3(gx, b.np), dim3(T), lds, s, b.desc, which, parity);
+  const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((b.maxJ + gpb - 1) / gpb, 8192));
+  hipLaunchKernelGGL(k_nnls_rows<R>, dim3(gx, b.np), dim3(T), lds, s, b.desc, parity);
   return hipGetLastError();
 }
 
@@ -2627,8 +2610,8 @@ hipError_t run_econ_fit(const BatchView& b, int parity, hipStream_t s) {
   P2_DISPATCH(b.R, return econ_t<RR>(b, parity, s))
 }
 
-hipError_t run_nnls(const BatchView& b, int which, int parity, hipStream_t s) {
-  P2_DISPATCH(b.R, return nnls_t<RR>(b, which, parity, s))
+hipError_t run_nnls(const BatchView& b, int parity, hipStream_t s) {
+  P2_DISPATCH(b.R, return nnls_t<RR>(b, parity, s))
 }
 
 hipError_t run_solve_n3(const BatchView& b, const PolarParams& pp, hipStream_t s) {
