@@ -639,15 +639,6 @@ __global__ void __launch_bounds__(256, NN ? PolarLds<R>::kMinWavesNN : PolarLds<
 // ---------------------------------------------------------------------------
 constexpr int kMode2Threads = 1024;
 
-#ifndef P2_M2_T10
-#define P2_M2_T10 2
-#endif
-#ifndef P2_M2_NT10
-#define P2_M2_NT10 0
-#endif
-#ifndef P2_M2_NT20
-#define P2_M2_NT20 0
-#endif
 #ifndef P2_M2D_QUEUE
 #define P2_M2D_QUEUE 16
 #endif
@@ -668,10 +659,7 @@ struct Mode2Lds {
   // lane may hold 256 VGPRs (the FP64 D row alone takes 2R of them)
   static constexpr int kMaxThreads = R <= 16 ? kMode2Threads : kMode2Threads / 2;
   // rows a lane gathers per step (register budget: T x LDV floats)
-  static constexpr int kRowsPerStep = R <= 6 ? 4 : (R <= 10 ? P2_M2_T10 : (R <= 20 ? 2 : 1));
-  // most frequent columns whose partial sums each lane keeps in registers
-  // (as many as the register budget of the rank's block size allows)
-  static constexpr int kTopReg = R <= 10 ? P2_M2_NT10 : (R == 20 ? P2_M2_NT20 : 0);
+  static constexpr int kRowsPerStep = R <= 20 ? 2 : 1;
   // floats before the group buffers: the hot partial sums, in FP64 (LDS
   // float atomics are carried out one lane at a time, about 3 cycles per
   // lane, while FP64 ones take about 24 cycles per wave instruction), rounded
@@ -777,18 +765,6 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
     __syncthreads();
     for (int q = threadIdx.x; q < hot * R; q += blockDim.x) shM2[q] = 0.0;
     __syncthreads();
-    // the kTopReg most frequent columns (ids 0.. after the relabelling) are
-    // summed in registers per lane and added to the LDS partial sums once per
-    // tile: under a skewed column distribution many lanes of one atomic
-    // instruction hit the same address, and LDS atomics to one address
-    // serialise
-    constexpr int NT = Mode2Lds<R>::kTopReg;
-    float top[NT > 0 ? NT : 1][R];
-#pragma unroll
-    for (int u = 0; u < (NT > 0 ? NT : 1); ++u) {
-#pragma unroll
-      for (int q = 0; q < R; ++q) top[u][q] = 0.f;
-    }
     if (L.live) {
       // H'(:, c) held as FP32: with E = F^T H' diag(w') formed in FP64, a
       // rounding dH of H' moves D = A E by Q_k dH diag(w'), and Q_k = A F^T
@@ -921,15 +897,7 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
                 j = (r == 0) ? j0[t] : (int)cl[zs[t] + r];
                 x = (r == 0) ? x0[t] : vl[zs[t] + r];
               }
-#pragma unroll
-              for (int u = 0; u < NT; ++u) {
-                const float xt = (j == u) ? x : 0.f;
-#pragma unroll
-                for (int q = 0; q < R; ++q) top[u][q] = fmaf(xt, (float)d[q], top[u][q]);
-              }
-              // hot columns below NT are summed in top[] above and flushed
-              // once per tile below
-              if (act && j >= NT && j < hot) {
+              if (act && j < hot) {
                 double* dst = shM2 + j * R;
 #pragma unroll
                 for (int q = 0; q < R; ++q) atomicAdd(dst + q, (double)x * d[q]);
@@ -945,14 +913,6 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
     }
     cold_flush<R>(M2, qj, qv, qcount[0]);
     if (L.lane == 0) qcount[0] = 0;
-#pragma unroll
-    for (int u = 0; u < NT; ++u) {
-      if (u < hot) {
-#pragma unroll
-        for (int q = 0; q < R; ++q)
-          if (top[u][q] != 0.f) atomicAdd(shM2 + u * R + q, (double)top[u][q]);
-      }
-    }
     __syncthreads();
     P2_GLOBAL float* mine = glob(D.part) + (int64_t)tile.slot * hot * R;
     for (int q = threadIdx.x; q < hot * R; q += blockDim.x) mine[q] = (float)shM2[q];
@@ -984,7 +944,6 @@ struct Mode2Dpp {
   static constexpr int kGroups = kWave / kLanes;  // subjects per wave
   // steps whose nonzero indices a lane loads at once (one nonzero per step)
   static constexpr int kChunk = P2_M2D_CHUNK;
-  static constexpr int kTopReg = R <= 10 ? P2_M2_NT10 : 0;
   // H' as floats after the hot partial sums
   static constexpr int kHFloats = (R * R + 3) & ~3;
   // per wave after H': a count, then up to kQueue staged cold updates (column
@@ -1063,13 +1022,6 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2_dpp(const ProbDesc* __r
     // condition number)
     for (int q = threadIdx.x; q < R * R; q += blockDim.x) shH[q] = (float)glob(D.H)[q];
     __syncthreads();
-    constexpr int NT = MD::kTopReg;
-    float top[NT > 0 ? NT : 1][R];
-#pragma unroll
-    for (int u = 0; u < (NT > 0 ? NT : 1); ++u) {
-#pragma unroll
-      for (int q = 0; q < R; ++q) top[u][q] = 0.f;
-    }
     for (int64_t pos = tile.k0 + gslot; pos < tile.k1; pos += gpb) {
       const int64_t k = subject_at(D, pos);
       const Subj s = X.subj(k);
@@ -1176,13 +1128,7 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2_dpp(const ProbDesc* __r
         for (int q = 0; q < R; ++q) d[q] = 0.0;
         dpp_guard();
         dpp_products<R>(d, e, a, std::make_integer_sequence<int, R>{});
-#pragma unroll
-        for (int w = 0; w < NT; ++w) {
-          const float xt = (j == w) ? x : 0.f;
-#pragma unroll
-          for (int q = 0; q < R; ++q) top[w][q] = fmaf(xt, (float)d[q], top[w][q]);
-        }
-        if (ok && j >= NT && j < hot) {
+        if (ok && j < hot) {
           double* dst = shM2 + j * R;
 #pragma unroll
           for (int q = 0; q < R; ++q) atomicAdd(dst + q, (double)x * d[q]);
@@ -1195,14 +1141,6 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2_dpp(const ProbDesc* __r
     }
     cold_flush<R>(M2, qj, qv, qcount[0]);
     if ((threadIdx.x & (kWave - 1)) == 0) qcount[0] = 0;
-#pragma unroll
-    for (int w = 0; w < NT; ++w) {
-      if (w < hot) {
-#pragma unroll
-        for (int q = 0; q < R; ++q)
-          if (top[w][q] != 0.f) atomicAdd(shM2 + w * R + q, (double)top[w][q]);
-      }
-    }
     __syncthreads();
     P2_GLOBAL float* mine = glob(D.part) + (int64_t)tile.slot * hot * R;
     for (int q = threadIdx.x; q < hot * R; q += blockDim.x) mine[q] = (float)shM2[q];
