@@ -752,12 +752,15 @@ __device__ __forceinline__ void factor_c(const double* Cs, double* Ec, double* s
 }
 
 // One factored Procrustes step.  On exit lane c (< R) holds (Y V)(:, c) in yv
-// and, if want_f, row c of F in fr.  S and S2 are group LDS scratch of
-// NC x R doubles each, dl of NC doubles.  vb is lane c's column of an
-// orthonormal start basis for the right singular vectors (e_c for a cold
-// start); on exit it holds this step's right singular vector at position c,
-// so that a following step with a nearby w (warm) starts from T V_prev,
-// whose columns are already nearly orthogonal, and needs fewer sweeps.
+// and, if want_f, row c of F at frs[c * R ..].  S and S2 are group LDS
+// scratch of NC x R doubles each, dl of NC doubles.  vbs[c * R ..] (group
+// LDS, NC x R doubles) is lane c's column of an orthonormal start basis for
+// the right singular vectors (read only when warm; a cold start uses e_c); on
+// exit it holds this step's right singular vector at position c, so that a
+// following step with a nearby w (warm) starts from T V_prev, whose columns
+// are already nearly orthogonal, and needs fewer sweeps.  The basis and F
+// live in LDS rather than registers: the R = 40 solve with accumulated
+// rotations already fills the register file.
 template <int R>
 __device__ __forceinline__ void polar_factored(const double* Ec, const double* sv,
                                                const double* isv, const double* w,
@@ -765,8 +768,7 @@ __device__ __forceinline__ void polar_factored(const double* Ec, const double* s
                                                double* dl, int c, int gbase, uint64_t gmask,
                                                double tau_s, double tol, double stop2,
                                                int max_sweeps, bool want_f, bool warm,
-                                               double (&vb)[R],
-                                               double (&yv)[R], double (&fr)[R]) {
+                                               double* vbs, double (&yv)[R], double* frs) {
   constexpr int NC = Geo<R>::NC;
   const bool real = c < R;
   const int cc = real ? c : 0;
@@ -795,12 +797,12 @@ __device__ __forceinline__ void polar_factored(const double* Ec, const double* s
     for (int p = 0; p < NC; ++p) g[p] = 0.0;
 #pragma nounroll
     for (int i = 0; i < R; ++i) {
-      const double b = vb[i];
+      const double b = vbs[c * R + i];
 #pragma unroll
       for (int p = 0; p < NC; ++p) g[p] = fma(S2[i * NC + p], b, g[p]);
     }
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = vb[i];
+    for (int i = 0; i < R; ++i) v[i] = vbs[c * R + i];
     wave_sync();
   } else {
 #pragma unroll
@@ -808,7 +810,7 @@ __device__ __forceinline__ void polar_factored(const double* Ec, const double* s
   }
   jacobi_onesided<R, NC>(g, v, c, gbase, gmask, true, tol, stop2, max_sweeps);
 #pragma unroll
-  for (int i = 0; i < R; ++i) vb[i] = v[i];
+  for (int i = 0; i < R; ++i) vbs[c * R + i] = v[i];
   double sig2 = 0.0;
 #pragma unroll
   for (int p = 0; p < NC; ++p) sig2 = fma(g[p], g[p], sig2);
@@ -862,6 +864,7 @@ __device__ __forceinline__ void polar_factored(const double* Ec, const double* s
 #pragma unroll
     for (int i = 0; i < R; ++i) S2[c * R + i] = zl[i];
     wave_sync();
+    double fr[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) fr[i] = 0.0;
     for (int q = 0; q < NC; ++q) {
@@ -869,6 +872,8 @@ __device__ __forceinline__ void polar_factored(const double* Ec, const double* s
 #pragma unroll
       for (int i = 0; i < R; ++i) fr[i] = fma(vqc, S2[q * R + i], fr[i]);
     }
+#pragma unroll
+    for (int i = 0; i < R; ++i) frs[c * R + i] = fr[i];
     wave_sync();
   }
 }

@@ -1665,8 +1665,10 @@ __global__ void __launch_bounds__(256) k_getq(XEnc X, int64_t k0, int64_t k1,
 template <int R>
 struct ProjLds {
   static constexpr int NC = Geo<R>::NC;
+  // C = A^T A until it is factored, then each lane's start basis for the
+  // SVD steps (NC x R), then F
   static constexpr int oCs = 0;
-  static constexpr int oEc = oCs + R * R;
+  static constexpr int oEc = oCs + NC * R;
   static constexpr int oS = oEc + NC * R;   // also the gather chunk
   static constexpr int oS2 = oS + NC * R;
   static constexpr int oSv = oS2 + NC * R;
@@ -1745,12 +1747,12 @@ __global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float*
     wave_sync();
     factor_c<R>(Cs, Ec, sv, isv, dl, c, L.gbase, L.gmask, pp.tau_c, pp.tol, pp.stop2,
                 pp.max_sweeps);
-    double yv[R], fr[R], vb[R], m3 = 0.0;
+    double yv[R], m3 = 0.0;
 #pragma nounroll
     for (int step = 0; step < n_steps; ++step) {
       // steps after the first start the SVD from the previous step's basis
       polar_factored<R>(Ec, sv, isv, wv, Hs, S, S2, dl, c, L.gbase, L.gmask, pp.tau_s, pp.tol,
-                        pp.stop2, pp.max_sweeps, step + 1 == n_steps, step > 0, vb, yv, fr);
+                        pp.stop2, pp.max_sweeps, step + 1 == n_steps, step > 0, Cs, yv, Cs);
       m3 = 0.0;
 #pragma unroll
       for (int i = 0; i < R; ++i) m3 = fma(Hs[i * R + cc], yv[i], m3);
@@ -1789,7 +1791,7 @@ __global__ void __launch_bounds__(256) k_project(XRaw X, int64_t K, const float*
           for (int ii = 0; ii < n; ++ii) {
             double q = 0.0;
 #pragma unroll
-            for (int p = 0; p < R; ++p) q = fma((double)Ab[ii * R + p], fr[p], q);
+            for (int p = 0; p < R; ++p) q = fma((double)Ab[ii * R + p], Cs[c * R + p], q);
             Qout[(s.r0 + i0 + ii) * R + c] = (float)q;
           }
         }
