@@ -86,7 +86,8 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_bytes": n * 4, "launches": 3}), flush=True)
 
 
-KERNEL_SOURCES = ("paper_1703_04219_amd/csrc/p2_kernels.hip", "paper_1703_04219_amd/csrc/p2_device.h",
+KERNEL_SOURCES = ("paper_1703_04219_amd/csrc/p2_rank_impl.h", "paper_1703_04219_amd/csrc/p2_ranks.hip",
+                  "paper_1703_04219_amd/csrc/p2_kernels.hip", "paper_1703_04219_amd/csrc/p2_device.h",
                   "paper_1703_04219_amd/csrc/p2_batch.h")
 
 

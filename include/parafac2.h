@@ -65,8 +65,9 @@ typedef struct parafac2_model parafac2_model;
  * accepted (they contribute nothing; the paper filters them, Sec.
  * "Challenges of PARAFAC2 on sparse data").  Limits of the library:
  * 1 <= I_k <= 65535, nnz of one subject <= 65535, J <= 65536,
- * K <= 2^31 - 1.  A subject with I_k < R (the paper runs such data at ranks
- * above its largest I_k, Table "table:data_stats") gets the economy
+ * K <= 2^31 - 1; every rank 1 <= R <= 40 is built.  A subject with
+ * I_k < R (the paper runs such data at ranks above its largest I_k, Table
+ * "table:data_stats") gets the economy
  * Procrustes factor Q_k = Z P^T from the thin SVD H S_k V^T X_k^T = P S Z^T:
  * an I_k x R matrix with orthonormal rows (Q_k Q_k^T = I), and the loss
  * counts ||Q_k H S_k V^T||_F with that Q_k.  A context with such subjects
@@ -256,8 +257,8 @@ int parafac2_get_profile(parafac2_ctx* c, double* ms, int64_t* launches);
  * 1 mode-3 / W update / next Procrustes step, 2 mode-2 scatter,
  * 3 projection, 4 Q assembly.  threads receives the workgroup size,
  * lds_bytes the dynamic LDS of one workgroup (for kernel 2 with the largest
- * hot-column set, whose size goes to max_hot).  P2_ENOTSUP for an R that is
- * not built. */
+ * hot-column set, whose size goes to max_hot).  P2_ENOTSUP for an R outside
+ * 1..40. */
 int parafac2_launch_config(int32_t R, int32_t kernel, int32_t* threads, int64_t* lds_bytes,
                            int32_t* max_hot);
 

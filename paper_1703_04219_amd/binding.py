@@ -21,7 +21,7 @@ P2_OK, P2_EINVAL, P2_ENOMEM, P2_EDEVICE, P2_ESTATE, P2_ENOTSUP, P2_EBUSY = 0, -1
 _STATUS = {P2_EINVAL: "EINVAL", P2_ENOMEM: "ENOMEM", P2_EDEVICE: "EDEVICE",
            P2_ESTATE: "ESTATE", P2_ENOTSUP: "ENOTSUP", P2_EBUSY: "EBUSY"}
 
-SUPPORTED_R = (1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 32, 40)
+SUPPORTED_R = tuple(range(1, 41))
 
 
 class Parafac2Error(RuntimeError):

@@ -226,18 +226,45 @@ hipError_t wupdate_t(const ProbDesc* desc, int64_t K, hipStream_t s) {
 
 #define P2_BDISPATCH(R, CALL)                 \
   switch (R) {                                \
-    case 1: { constexpr int RR = 1; CALL; }   \
-    case 2: { constexpr int RR = 2; CALL; }   \
-    case 3: { constexpr int RR = 3; CALL; }   \
-    case 4: { constexpr int RR = 4; CALL; }   \
-    case 5: { constexpr int RR = 5; CALL; }   \
-    case 6: { constexpr int RR = 6; CALL; }   \
-    case 8: { constexpr int RR = 8; CALL; }   \
+    case 1: { constexpr int RR = 1; CALL; } \
+    case 2: { constexpr int RR = 2; CALL; } \
+    case 3: { constexpr int RR = 3; CALL; } \
+    case 4: { constexpr int RR = 4; CALL; } \
+    case 5: { constexpr int RR = 5; CALL; } \
+    case 6: { constexpr int RR = 6; CALL; } \
+    case 7: { constexpr int RR = 7; CALL; } \
+    case 8: { constexpr int RR = 8; CALL; } \
+    case 9: { constexpr int RR = 9; CALL; } \
     case 10: { constexpr int RR = 10; CALL; } \
+    case 11: { constexpr int RR = 11; CALL; } \
     case 12: { constexpr int RR = 12; CALL; } \
+    case 13: { constexpr int RR = 13; CALL; } \
+    case 14: { constexpr int RR = 14; CALL; } \
+    case 15: { constexpr int RR = 15; CALL; } \
     case 16: { constexpr int RR = 16; CALL; } \
+    case 17: { constexpr int RR = 17; CALL; } \
+    case 18: { constexpr int RR = 18; CALL; } \
+    case 19: { constexpr int RR = 19; CALL; } \
     case 20: { constexpr int RR = 20; CALL; } \
+    case 21: { constexpr int RR = 21; CALL; } \
+    case 22: { constexpr int RR = 22; CALL; } \
+    case 23: { constexpr int RR = 23; CALL; } \
+    case 24: { constexpr int RR = 24; CALL; } \
+    case 25: { constexpr int RR = 25; CALL; } \
+    case 26: { constexpr int RR = 26; CALL; } \
+    case 27: { constexpr int RR = 27; CALL; } \
+    case 28: { constexpr int RR = 28; CALL; } \
+    case 29: { constexpr int RR = 29; CALL; } \
+    case 30: { constexpr int RR = 30; CALL; } \
+    case 31: { constexpr int RR = 31; CALL; } \
     case 32: { constexpr int RR = 32; CALL; } \
+    case 33: { constexpr int RR = 33; CALL; } \
+    case 34: { constexpr int RR = 34; CALL; } \
+    case 35: { constexpr int RR = 35; CALL; } \
+    case 36: { constexpr int RR = 36; CALL; } \
+    case 37: { constexpr int RR = 37; CALL; } \
+    case 38: { constexpr int RR = 38; CALL; } \
+    case 39: { constexpr int RR = 39; CALL; } \
     case 40: { constexpr int RR = 40; CALL; } \
     default: return hipErrorInvalidValue;     \
   }

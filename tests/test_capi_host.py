@@ -96,7 +96,7 @@ def test_validate_host_rank_rules():
     sp = np.concatenate([[0], X.subj_ptr])
     rc, msg = B.parafac2_validate_host(sp, X.row_ptr, X.col, X.val, X.J, 5)
     assert rc == B.P2_EINVAL and "no rows" in msg
-    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 7)
+    rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 41)
     assert rc == B.P2_ENOTSUP
     rc, msg = B.parafac2_validate_host(X.subj_ptr, X.row_ptr, X.col, X.val, X.J, 0)
     assert rc == B.P2_EINVAL
@@ -143,9 +143,10 @@ def test_workspace_size_is_sane(R):
 
 
 def test_launch_config_rejects_unbuilt_rank():
-    with pytest.raises(B.Parafac2Error) as e:
-        B.parafac2_launch_config(7, 0)
-    assert e.value.code == B.P2_ENOTSUP
+    for R in (0, 41, 64):
+        with pytest.raises(B.Parafac2Error) as e:
+            B.parafac2_launch_config(R, 0)
+        assert e.value.code in (B.P2_ENOTSUP, B.P2_EINVAL)
 
 
 def test_init_rejects_a_short_workspace_before_touching_the_gpu():

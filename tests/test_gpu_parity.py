@@ -138,11 +138,30 @@ def test_mode2_hot_column_counts(R, hot_cols):
     _compare_one_iteration(X, R, H0, V0, W0, hot_cols=hot_cols)
 
 
-@pytest.mark.parametrize("R", [1, 2, 3, 4, 6, 8, 12, 16, 20, 32])
+@pytest.mark.parametrize("R", [r for r in B.SUPPORTED_R if r not in (10, 40)])
 def test_other_ranks_one_iteration(R):
-    X = gen_slices(300, 150, (R, R + 12), _poisson_plus_one(3.0), "zipf", [9000 + R])
+    # J = 400 columns: with J = 150 the R = 39 case draws a subject with
+    # kappa(B_k) = 8.9e6, whose Procrustes factor alone moves M2 by 8.6e-6
+    # and V by 1.8e-4 of their largest entries (the per-subject rows stay
+    # within their kappa bars); such subjects are the kappa-binned tests'
+    # business, this one covers every rank's kernels
+    X = gen_slices(300, 400, (R, R + 12), _poisson_plus_one(3.0), "zipf", [9000 + R])
     H0, V0, W0 = gen_init(X.J, X.K, R, [9000 + R, 1])
     _compare_one_iteration(X, R, H0, V0, W0)
+
+
+@pytest.mark.parametrize("R", [7, 13, 17, 25, 33, 39])
+def test_other_ranks_fit_trajectory(R):
+    # after the first iteration each Procrustes step runs inside the mode-3
+    # pass of the iteration before: odd ranks and ranks between the built
+    # lane-group sizes take that path too
+    X = gen_slices(300, 400, (R, R + 12), _poisson_plus_one(3.0), "zipf", [9100 + R])
+    H0, V0, W0 = gen_init(X.J, X.K, R, [9100 + R, 1])
+    _, _, _, hist = O.run(_xs(X), H0, V0, W0, 4, dense_loss=False)
+    ofits = np.array([h["fit"] for h in hist])
+    _, gfits = _gpu_run(X, R, H0, V0, W0, 4)
+    print(f"R={R} fit oracle", ofits, "gpu", gfits, flush=True)
+    assert np.max(np.abs(gfits - ofits)) <= 1e-5
 
 
 def _with_empty_rows(X, every=3):
@@ -289,6 +308,22 @@ def test_projection_matches_oracle():
     check_rows("projection w", w, ws, kap)
     nx = np.array([float(x.data @ x.data) for x in Xs])
     assert np.max(np.abs(loss - np.array(ls)) / nx) <= 1e-5
+
+
+@pytest.mark.parametrize("R", [7, 17, 33])
+def test_projection_other_ranks(R):
+    V, H = gen_serving_model(J=800, R=R, density=0.2, seed=(170304219, 50 + R))
+    _, Xr = gen_serving_requests(16, J=800, R=R, seed=(170304219, 50 + R))
+    Q, w, loss = B.Model(V, H).project(B.DeviceSlices.from_slices(Xr), n_steps=10)
+    torch.cuda.synchronize()
+    w = w.cpu().numpy().astype(np.float64)
+    Xs = _xs(Xr)
+    ws = np.array([O.project(Xs[k], V.astype(np.float64), H, n_steps=10)[1]
+                   for k in range(Xr.K)])
+    err = rel(w, ws)
+    print(f"R={R} projection w rel err", err, flush=True)
+    assert err <= 1e-4
+    check_rows("projection w", w, ws, kappa_of(Xs, H, V.astype(np.float64), ws))
 
 
 def test_projection_alone_equals_in_the_mix():
