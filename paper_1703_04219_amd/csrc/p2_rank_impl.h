@@ -232,9 +232,13 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
         wave_sync();
         double f[R], y[R];
         float* Ek = WARM ? D.E + k * (Geo<R>::NC * R) : nullptr;
+        // the polar step at raised wave priority: a wave in its chain of
+        // dependent FP64 steps issues ahead of waves waiting on gathers
+        __builtin_amdgcn_s_setprio(1);
         polar_rxr<R, WARM>(Cs, wv, Hs, S, dl, Ek, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
                      pp.stop2,
                      pp.max_sweeps, f, y);
+        __builtin_amdgcn_s_setprio(0);
         if (c < R) {
           P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
@@ -595,9 +599,12 @@ __global__ void __launch_bounds__(256, NN ? PolarLds<R>::kMinWavesNN : PolarLds<
           wave_sync();
           double f[R], y[R];
           float* Ek = WARM ? D.E + k * (Geo<R>::NC * R) : nullptr;
+          // raised wave priority for the polar step, as in k_alpha
+          __builtin_amdgcn_s_setprio(1);
           polar_rxr<R, WARM>(SF, wv, Hs, SP, dl, Ek, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
                        pp.stop2,
                        pp.max_sweeps, f, y);
+          __builtin_amdgcn_s_setprio(0);
           if (real) {
             P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
