@@ -838,6 +838,10 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
         const P2_GLOBAL float* __restrict__ vl = glob(X.val) + s.z0;
 #pragma nounroll
         for (int ib = 0; ib < s.nrows; ib += T * NC) {
+          // the step's loads at raised wave priority, its products and
+          // updates at the normal one: a wave whose loads are ready issues the
+          // next ones ahead of the SIMD's waves that are computing
+          __builtin_amdgcn_s_setprio(1);
           int zs[T], ze[T];
 #pragma unroll
           for (int t = 0; t < T; ++t) {
@@ -882,6 +886,7 @@ __global__ void __launch_bounds__(Mode2Lds<R>::kMaxThreads) k_mode2(const ProbDe
               }
             }
           }
+          __builtin_amdgcn_s_setprio(0);
 #pragma unroll
           for (int t = 0; t < T; ++t) {
             const int nz = ze[t] - zs[t];  // 0 for rows past the subject
@@ -1082,6 +1087,9 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2_dpp(const ProbDesc* __r
       constexpr int NB = MD::kChunk;
 #pragma nounroll
       for (int zc = 0; zc < s.nnz; zc += G * NB) {
+        // loads at raised wave priority, products and updates at the normal
+        // one (as in k_mode2)
+        __builtin_amdgcn_s_setprio(1);
         uint32_t rjc[NB];  // row << 16 | column
         float xc[NB];
 #pragma unroll
@@ -1108,6 +1116,7 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2_dpp(const ProbDesc* __r
           xc[u] = xc[u + 1];
         }
         // V(j, :) and the row's bounds, in flight together
+        __builtin_amdgcn_s_setprio(1);
         p2_f4 v4[LDV / 4];
         const float* vr = V + (size_t)j * LDV;
 #pragma unroll
@@ -1139,6 +1148,7 @@ __global__ void __launch_bounds__(kMode2Threads) k_mode2_dpp(const ProbDesc* __r
         }
         // D(i, :) = A(i, :) E_k for every lane of the group (lanes past the
         // subject have A = 0)
+        __builtin_amdgcn_s_setprio(0);
         double d[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) d[q] = 0.0;
