@@ -721,7 +721,10 @@ __device__ __forceinline__ void cold_stage(bool cold, int j, float x, const DT (
   int base = qcount[0];
   for (int done = 0; done < ncold;) {  // the same on every active lane
     if (base == QN) {
+      // the flush's coalesced updates go out ahead of the SIMD's other waves
+      __builtin_amdgcn_s_setprio(2);
       cold_flush<R>(M2, qj, qv, QN);
+      __builtin_amdgcn_s_setprio(0);
       base = 0;
     }
     const int take = min(QN - base, ncold - done);
