@@ -4,16 +4,17 @@
 // that the subsets compile in parallel; p2_kernels.hip dispatches on R
 // through them and holds the rank-independent kernels.
 //
-//
 // Per-iteration kernel sequence (see p2_capi.hip for the driver):
 //   k_alpha     (first iteration only) gather A_k = X_k V, C_k = A_k^T A_k,
 //               Procrustes polar in FP64, F_k = G_k^{-1/2} H S_k, mode-1
 //               partial (Y_k V) S_k accumulated into M1;
-//   k_gram_tall W^T W;
+//   k_gram      W^T W;
 //   k_solve_h   H <- M1 ((W^T W) * (V^T V))^+, normalise, prepare N2^+;
-//   k_mode2     regather A_k, D_k = A_k F_k^T H S_k, scatter X_k^T D_k into M2;
-//   k_vupdate / k_gram_tall / k_solve_n3 / k_vscale   V <- M2 N2^+, normalise,
-//               N3 = (V^T V) * (H^T H) and its pseudo-inverse;
+//   k_mode2_dpp (R <= 16) or k_mode2, then k_mode2_reduce: regather A_k,
+//               D_k = A_k F_k^T H S_k, scatter X_k^T D_k into M2;
+//   k_vupdate (or k_nnls_rows) / k_gram / k_solve_n3 / k_vscale
+//               V <- M2 N2^+, normalise, N3 = (V^T V) * (H^T H) and its
+//               pseudo-inverse;
 //   k_gamma     regather A_k against V_t and V_{t+1}: mode-3 row
 //               diag(H^T F_k A_k^T A'_k), W row update, fit terms, and the
 //               next iteration's Procrustes step and mode-1 partial from
