@@ -233,13 +233,9 @@ __global__ void __launch_bounds__(256) k_alpha(const ProbDesc* __restrict__ P,
         wave_sync();
         double f[R], y[R];
         float* Ek = WARM ? D.E + k * (Geo<R>::NC * R) : nullptr;
-        // the polar step at raised wave priority: a wave in its chain of
-        // dependent FP64 steps issues ahead of waves waiting on gathers
-        __builtin_amdgcn_s_setprio(1);
         polar_rxr<R, WARM>(Cs, wv, Hs, S, dl, Ek, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
                      pp.stop2,
                      pp.max_sweeps, f, y);
-        __builtin_amdgcn_s_setprio(0);
         if (c < R) {
           P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
@@ -600,12 +596,16 @@ __global__ void __launch_bounds__(256, NN ? PolarLds<R>::kMinWavesNN : PolarLds<
           wave_sync();
           double f[R], y[R];
           float* Ek = WARM ? D.E + k * (Geo<R>::NC * R) : nullptr;
-          // raised wave priority for the polar step, as in k_alpha
-          __builtin_amdgcn_s_setprio(1);
+          // at ranks up to 16 the polar step runs at raised wave priority: a
+          // wave in its chain of dependent FP64 steps issues ahead of waves
+          // waiting on gathers (measured: the pass 1.6 % faster at R = 10,
+          // unchanged at R = 12, 16 and 20, and 2 % slower at R = 40, which
+          // runs one wave per SIMD)
+          if constexpr (R <= 16) __builtin_amdgcn_s_setprio(1);
           polar_rxr<R, WARM>(SF, wv, Hs, SP, dl, Ek, c, L.gbase, L.gmask, true, pp.tau_polar, pp.tol,
                        pp.stop2,
                        pp.max_sweeps, f, y);
-          __builtin_amdgcn_s_setprio(0);
+          if constexpr (R <= 16) __builtin_amdgcn_s_setprio(0);
           if (real) {
             P2_GLOBAL double* Fk = glob(F) + (size_t)k * R * R + (size_t)c * R;
 #pragma unroll
