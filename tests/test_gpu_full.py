@@ -50,7 +50,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("cfg,sched", [
-    (2, dict(tile_rounds=4, dynamic=1, m2_tiles=256)),
+    (2, dict(tile_rounds=8, dynamic=1, m2_tiles=256)),
     (2, dict()),
     (3, dict(tile_rounds=16, dynamic=1)),
 ])
