@@ -96,8 +96,9 @@ def test_full_size_matches_oracle(cfg, sched):
 def test_full_size_batch_equals_problems_alone():
     # the 64-problem workload at full size (K log-uniform in [1000, 50000],
     # R in {5, 10, 20}, about 348M nonzeros), batched in the schedule the
-    # bench's autotuner settles on (graph replay, dynamic tiles, 768-thread
-    # mode-2 blocks), against each problem run on its own context: one
+    # bench's autotuner settles on (graph replay, dynamic tiles of one round,
+    # the default mode-2 blocks), against each problem run on its own
+    # context: one
     # iteration from the same state agrees to 1e-5 (only the order of float
     # atomics differs)
     from datagen.synth import gen_batched_problem, gen_batched_specs
@@ -119,8 +120,7 @@ def test_full_size_batch_equals_problems_alone():
     torch.cuda.synchronize()
     ctxs = [B.Context(B.DeviceSlices.from_slices(X), R, H0, V0, W0)
             for X, R, H0, V0, W0 in probs]
-    batch = B.Batch(ctxs, B.make_sched(tile_rounds=2, dynamic=1, graph=1, m2_threads=768,
-                                       m2_blocks=1))
+    batch = B.Batch(ctxs, B.make_sched(tile_rounds=1, dynamic=1, graph=1))
     batch.iterate(1)
     torch.cuda.synchronize()
     worst = 0.0
