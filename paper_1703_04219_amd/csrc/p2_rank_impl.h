@@ -1946,15 +1946,21 @@ template <int R> constexpr size_t mode2_ebytes_at(int threads) {
   if constexpr (kMode2UsesDpp<R>) return 0;
   return (size_t)(threads / kWave) * Geo<R>::GPW * mode2_group<R>();
 }
+// Share of a block's LDS budget that the groups' E_k buffers of the R > 16
+// mode-2 kernel may take; the rest holds the hot-column sums.  The pass is
+// bound by the latency of its loads, so waves in flight count for more than
+// hot columns (on the K = 1M slices, R = 32: 29.0 ms with half of the LDS,
+// 19.1 with 3/4, 17.2 with 7/8; R = 40: 38.5, 31.0, 31.0 ms).
+constexpr size_t mode2_ebudget(size_t budget) { return budget * 7 / 8; }
+
 // Default mode-2 block: for R > 16 the most waves whose E_k buffers fit in
-// half of the LDS (the rest holds the hot-column sums).  The pass is bound by
-// the latency of its loads, so waves in flight count for more than hot
-// columns: at R = 40, 384 threads against 256 took it from 28.9 to 23.4 ms
-// on 250K subjects.
+// that share.
 template <int R> constexpr int mode2_threads() {
   if constexpr (kMode2UsesDpp<R>) return kMode2Threads;
   for (int t = Mode2Lds<R>::kMaxThreads; t >= kWave; t -= kWave)
-    if (mode2_ebytes_at<R>(t) <= kLdsBudget / 2) return t;
+    if (mode2_ebytes_at<R>(t) <= mode2_ebudget(kLdsBudget) &&
+        mode2_groups_bytes_at<R>(t) + 2048 <= kLdsBudget)
+      return t;
   return 0;
 }
 // subject groups per wave of the rank's mode-2 kernel
@@ -2062,7 +2068,9 @@ hipError_t plan_t(BatchView& b) {
   int threads = b.m2_threads > 0 ? b.m2_threads : mode2_threads<R>();
   threads = threads / kWave * kWave;
   if (threads > Mode2Lds<R>::kMaxThreads) threads = Mode2Lds<R>::kMaxThreads;
-  while (threads > kWave && mode2_ebytes_at<R>(threads) > budget / 2) threads -= kWave;
+  while (threads > kWave && (mode2_ebytes_at<R>(threads) > mode2_ebudget(budget) ||
+                             mode2_groups_bytes_at<R>(threads) + 2048 > budget))
+    threads -= kWave;
   if (threads < kWave || mode2_groups_bytes_at<R>(threads) + 2048 > budget)
     return hipErrorInvalidConfiguration;
   int hot = (int)((budget - 2048 - mode2_groups_bytes_at<R>(threads)) / (sizeof(double) * R));
